@@ -1,0 +1,94 @@
+"""Dense-matrix brute force of the residual -- TEST INFRASTRUCTURE ONLY.
+
+A second, independent and deliberately naive evaluation of the same residual
+as ``tgv_oracle.cpp`` for tiny grids (16^3): each 4th-order central operator
+(Sec. 2.3.1) is an explicit dense n x n periodic circulant matrix built from
+its stencil weights, and is applied along one axis with ``numpy.tensordot``.
+No code is shared with the C++ oracle or with the GPU path.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def circulant(n: int, weights: dict, scale: float) -> np.ndarray:
+    """Dense periodic matrix M with (M f)_i = scale * sum_s weights[s] f_{(i+s) mod n}."""
+    M = np.zeros((n, n))
+    for i in range(n):
+        for s, w in weights.items():
+            M[i, (i + s) % n] += w * scale
+    return M
+
+
+def d1_matrix(n: int, h: float) -> np.ndarray:
+    return circulant(n, {-2: 1.0, -1: -8.0, 1: 8.0, 2: -1.0}, 1.0 / (12.0 * h))
+
+
+def d2_matrix(n: int, h: float) -> np.ndarray:
+    return circulant(n, {-2: -1.0, -1: 16.0, 0: -30.0, 1: 16.0, 2: -1.0}, 1.0 / (12.0 * h * h))
+
+
+class Ops:
+    """Axis operators on fields shaped (nz, ny, nx); axis 0 = x, 1 = y, 2 = z."""
+
+    def __init__(self, n, L):
+        self.D1 = [d1_matrix(n[d], L[d] / n[d]) for d in range(3)]
+        self.D2 = [d2_matrix(n[d], L[d] / n[d]) for d in range(3)]
+
+    @staticmethod
+    def _apply(M, f, axis):
+        ax = 2 - axis  # array axis of physical axis
+        return np.moveaxis(np.tensordot(M, f, axes=([1], [ax])), 0, ax)
+
+    def d1(self, f, axis):
+        return self._apply(self.D1[axis], f, axis)
+
+    def d2(self, f, axis):
+        return self._apply(self.D2[axis], f, axis)
+
+
+def residual(q, n, L, gamma, mach, re, pr, viscous=True):
+    """R = -C - P + V for Q = (rho, m1, m2, m3, rho E) shaped (5, nz, ny, nx)."""
+    ops = Ops(n, L)
+    rho, m, E = q[0], [q[1], q[2], q[3]], q[4]
+    u = [m[a] / rho for a in range(3)]
+    p = (gamma - 1.0) * (E - 0.5 * (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]))
+    T = gamma * mach ** 2 * p / rho
+    cons = [rho, m[0], m[1], m[2], E]
+    R = np.zeros_like(q)
+    for f, qf in enumerate(cons):
+        C = sum(0.5 * (ops.d1(qf * u[d], d) + u[d] * ops.d1(qf, d) + qf * ops.d1(u[d], d))
+                for d in range(3))
+        R[f] -= C
+    for a in range(3):
+        R[a + 1] -= ops.d1(p, a)
+    R[4] -= sum(ops.d1(p * u[d], d) for d in range(3))
+    if viscous:
+        G = [[ops.d1(u[a], d) for d in range(3)] for a in range(3)]
+        div = G[0][0] + G[1][1] + G[2][2]
+        Vm = []
+        for a in range(3):
+            lap = sum(ops.d2(u[a], d) for d in range(3))
+            X = ops.d2(u[a], a) + sum(ops.d1(ops.d1(u[d], d), a) for d in range(3) if d != a)
+            Vm.append((lap + X / 3.0) / re)
+            R[a + 1] += Vm[a]
+        VE = sum(u[a] * Vm[a] for a in range(3))
+        for a in range(3):
+            for d in range(3):
+                tau = (G[a][d] + G[d][a] - (2.0 / 3.0 if a == d else 0.0) * div) / re
+                VE = VE + tau * G[a][d]
+        kappa = 1.0 / ((gamma - 1.0) * mach ** 2 * pr * re)
+        VE = VE + kappa * sum(ops.d2(T, d) for d in range(3))
+        R[4] += VE
+    return R
+
+
+def dissipation(q, n, L, re):
+    """eps^S = (1/Re) <|curl u|^2> with dense D1 matrices."""
+    ops = Ops(n, L)
+    u = [q[a + 1] / q[0] for a in range(3)]
+    G = [[ops.d1(u[a], d) for d in range(3)] for a in range(3)]
+    w1 = G[2][1] - G[1][2]
+    w2 = G[0][2] - G[2][0]
+    w3 = G[1][0] - G[0][1]
+    return float(np.mean(w1 ** 2 + w2 ** 2 + w3 ** 2) / re)
