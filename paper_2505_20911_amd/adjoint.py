@@ -1,0 +1,160 @@
+"""Gradient of the time-integrated dissipation with respect to the initial
+state, by the discrete adjoint of the RK3 time step with binomial
+checkpointing, exposed as a ``torch.autograd.Function``.
+
+Objective (trapezoid rule over the step boundaries, eps^S as in Sec. 4.1):
+    J = dt * sum_{n=0}^{l} w_n eps^S(Q^n),   w_0 = w_l = 1/2, else 1.
+Reverse of one step (Sec. 3.1 update, read backwards): with stage inputs
+Y_0 = Q^{n-1}, Y_1, Y_2 re-taped from the restored state and zeta = 0,
+for i = 2, 1, 0:  zeta += B_i Q_bar ; R_bar = dt zeta ; zeta <- A_i zeta ;
+Q_bar += (dR/dQ)(Y_i)^T R_bar   (rk_stage_adjoint, ns_residual_adjoint),
+then Q_bar += dt w_{n-1} d(eps^S)/dQ(Y_0)   (flow_integrals_adjoint).
+Every arithmetic step runs in libtgv's kernels; this module sequences the
+calls and the snapshot copies.  The map from a velocity field to Q^0 is left
+to torch autograd (see ``state_from_velocity``), so gradients flow on to u0.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import revolve, tgv
+from .tgv import Params, Prec
+
+
+def state_from_velocity(u0: torch.Tensor, rho0: torch.Tensor, p0: torch.Tensor, gamma: float) -> torch.Tensor:
+    """Q^0 from a velocity field (3, nz, ny, nx) with density and pressure held
+    fixed: (rho0, rho0 u0, p0/(gamma-1) + rho0 |u0|^2 / 2).  Plain torch ops,
+    differentiable, so torch autograd carries dJ/dQ^0 on to u0."""
+    m = rho0.unsqueeze(0) * u0
+    E = p0 / (gamma - 1.0) + 0.5 * rho0 * (u0 * u0).sum(0)
+    return torch.cat([rho0.unsqueeze(0), m, E.unsqueeze(0)], 0).contiguous()
+
+
+class CheckpointedDissipation:
+    """Forward sweep and revolve-scheduled reverse sweep on one GPU."""
+
+    def __init__(self, params: Params, prec: Prec, dt: float, nsteps: int, slots: int = 20, device="cuda"):
+        if prec.q != prec.qt or prec.q != prec.r or prec.q != prec.compute:
+            raise ValueError("the adjoint runs with a single storage/compute type (DP or SP preset)")
+        self.params, self.prec, self.dt, self.l = params, prec, float(dt), int(nsteps)
+        self.slots = min(int(slots), max(self.l - 1, 0))
+        self.device = torch.device(device)
+        shape, dt_ = params.shape, prec.q
+        mk = lambda: torch.empty(shape, dtype=dt_, device=self.device)
+        self.cur, self.qt, self.r = mk(), torch.zeros(shape, dtype=dt_, device=self.device), mk()
+        self.Y = [mk(), mk(), mk()]
+        self.qbar, self.zeta, self.rbar = mk(), mk(), mk()
+        self.snap = [mk() for _ in range(self.slots)]
+        self.qlast = mk()
+        nb = tgv.flow_integrals_workspace_bytes(params)
+        self.iwork = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        self.awork = torch.empty(tgv.ns_residual_adjoint_workspace_bytes(params, prec) // 8 + 1,
+                                 dtype=torch.float64, device=self.device)
+        self.ewrk = torch.empty(tgv.flow_integrals_adjoint_workspace_bytes(params, prec) // 8 + 1,
+                                dtype=torch.float64, device=self.device)
+        self.eps = torch.zeros((self.l + 1, 8), dtype=torch.float64, device=self.device)
+        self.actions = revolve.schedule(self.l, self.slots) if self.l > 0 else []
+        self.advances = 0
+
+    def weight(self, n: int) -> float:
+        return 0.5 if n in (0, self.l) else 1.0
+
+    # -- forward pieces
+    def _advance(self, q: torch.Tensor) -> None:
+        for i in range(3):
+            tgv.ns_residual(self.params, self.prec, q, self.r)
+            tgv.rk_stage(self.params, self.prec, i, self.dt, q, self.qt, self.r)
+        self.advances += 1
+
+    def _integrals(self, q: torch.Tensor, n: int) -> None:
+        tgv.flow_integrals(self.params, self.prec, q, self.iwork, self.eps[n])
+
+    def _slot(self, s: int, q0: torch.Tensor) -> torch.Tensor:
+        return q0 if s < 0 else self.snap[s]
+
+    def forward(self, q0: torch.Tensor) -> float:
+        """Runs the schedule's first descent (storing its snapshots) and one
+        extra step to Q^l; returns J."""
+        self.cur.copy_(q0)
+        self._integrals(self.cur, 0)
+        n = 0
+        self._pos = 0
+        for k, act in enumerate(self.actions):
+            if act[0] == "reverse":
+                self._pos = k
+                break
+            if act[0] == "advance":
+                self._advance(self.cur)
+                n += 1
+                self._integrals(self.cur, n)
+            elif act[0] == "store":
+                self.snap[act[1]].copy_(self.cur)
+            elif act[0] in ("restore", "free"):  # cannot occur before the first reversal
+                raise AssertionError(act)
+        if self.l > 0:
+            self.qlast.copy_(self.cur)  # Q^{l-1}; advance a copy to Q^l for eps^S(Q^l)
+            self._advance(self.qlast)
+            self._integrals(self.qlast, self.l)
+        eps = self.eps[:, 2].cpu().numpy()
+        w = np.ones(self.l + 1)
+        w[0] = w[-1] = 0.5
+        return float(self.dt * np.dot(w, eps)) if self.l > 0 else 0.0
+
+    # -- reverse pieces
+    def _reverse_step(self, n: int, scale: float) -> None:
+        """Reverse step n; the current state is Q^{n-1}."""
+        for i in range(3):
+            self.Y[i].copy_(self.cur)
+            tgv.ns_residual(self.params, self.prec, self.cur, self.r)
+            tgv.rk_stage(self.params, self.prec, i, self.dt, self.cur, self.qt, self.r)
+        for i in (2, 1, 0):
+            tgv.rk_stage_adjoint(self.params, self.prec, i, self.dt, self.qbar, self.zeta, self.rbar)
+            tgv.ns_residual_adjoint(self.params, self.prec, self.Y[i], self.rbar, self.qbar, self.awork)
+        tgv.flow_integrals_adjoint(self.params, self.prec, self.Y[0], scale * self.dt * self.weight(n - 1),
+                                   self.qbar, self.ewrk)
+
+    def backward(self, q0: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """Returns scale * dJ/dQ^0 (a new tensor)."""
+        self.qbar.zero_()
+        self.zeta.zero_()
+        if self.l == 0:
+            tgv.flow_integrals_adjoint(self.params, self.prec, q0, scale * self.dt, self.qbar, self.ewrk)
+            return self.qbar.clone()
+        tgv.flow_integrals_adjoint(self.params, self.prec, self.qlast, scale * self.dt * self.weight(self.l),
+                                   self.qbar, self.ewrk)
+        for act in self.actions[self._pos:]:
+            kind = act[0]
+            if kind == "advance":
+                self._advance(self.cur)
+            elif kind == "store":
+                self.snap[act[1]].copy_(self.cur)
+            elif kind == "restore":
+                self.cur.copy_(self._slot(act[1], q0))
+            elif kind == "reverse":
+                self._reverse_step(act[1], scale)
+        return self.qbar.clone()
+
+
+class TGVDissipation(torch.autograd.Function):
+    """J(Q^0) = dt sum_n w_n eps^S(Q^n) over `nsteps` RK3 steps; backward
+    returns dJ/dQ^0 through the discrete adjoint with revolve checkpointing."""
+
+    @staticmethod
+    def forward(ctx, q0: torch.Tensor, runner: CheckpointedDissipation):
+        q0c = q0.detach().contiguous()
+        J = runner.forward(q0c)
+        ctx.runner = runner
+        ctx.save_for_backward(q0c)
+        return torch.tensor(J, dtype=torch.float64, device=q0.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (q0,) = ctx.saved_tensors
+        g = ctx.runner.backward(q0, float(gJ))
+        return g, None
+
+
+def dissipation(q0: torch.Tensor, params: Params, prec: Prec, dt: float, nsteps: int, slots: int = 20):
+    runner = CheckpointedDissipation(params, prec, dt, nsteps, slots, device=q0.device)
+    return TGVDissipation.apply(q0, runner)

@@ -1,0 +1,388 @@
+// Discrete adjoint of the residual, of the RK stage and of eps^S.
+//
+// For the residual R(Q) the adjoint Q_bar += (dR/dQ)^T R_bar is written in
+// gather form.  With D the antisymmetric 4th-order first difference,
+// D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
+// stencil term of the forward residual turns into a stencil of R_bar-weighted
+// pointwise fields evaluated around the output point, plus pointwise terms.
+// The only coefficient that needs forward derivatives at a neighbour is the
+// adjoint of the viscous work sum tau_ad G_ad, G_bar_ad = 2 R_bar_E tau_ad
+// (symmetric): pass A stores its 6 components, pass B gathers everything.
+#include "tgv_device.h"
+#include "tgv_kernels.h"
+
+namespace tgv {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ long long nb(const Grid& g, long long id, const int ijk[3], int d, int s) {
+  if (d == 0) {
+    int t = ijk[0] + s;
+    t += (t < 0) ? g.nx : 0;
+    t -= (t >= g.nx) ? g.nx : 0;
+    return id + (t - ijk[0]);
+  } else if (d == 1) {
+    int t = ijk[1] + s;
+    t += (t < 0) ? g.ny : 0;
+    t -= (t >= g.ny) ? g.ny : 0;
+    return id + (long long)(t - ijk[1]) * g.nx;
+  }
+  int t = ijk[2] + s;
+  t += (t < 0) ? g.nz : 0;
+  t -= (t >= g.nz) ? g.nz : 0;
+  return id + (long long)(t - ijk[2]) * g.plane;
+}
+
+__device__ __forceinline__ void coords(const Grid& g, long long id, int ijk[3]) {
+  ijk[0] = (int)(id % g.nx);
+  ijk[1] = (int)((id / g.nx) % g.ny);
+  ijk[2] = (int)(id / g.plane);
+}
+
+template <class T>
+__device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T s) {
+  return s * (T(8) * (p1 - m1) - (p2 - m2));
+}
+template <class T>
+__device__ __forceinline__ T D2(T m2, T m1, T c0, T p1, T p2, T s) {
+  return s * (T(16) * ((p1 - c0) + (m1 - c0)) - ((p2 - c0) + (m2 - c0)));
+}
+
+// Index of the symmetric pair (a, d) in the 6-component storage.
+__device__ __forceinline__ int sym(int a, int d) {
+  if (a == d) return a;
+  const int lo = a < d ? a : d, hi = a < d ? d : a;
+  return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
+}
+
+// Pass A: G_bar_ad = 2 R_bar_E tau_ad at every point.
+template <class T>
+__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, Coef<T> c, const T* __restrict__ q,
+                                                       const T* __restrict__ rb, T* __restrict__ gbar) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.N) return;
+  int ijk[3];
+  coords(g, id, ijk);
+  T G[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T u[4][3];
+    const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const long long n = nb(g, id, ijk, d, offs[s]);
+      const T ir = T(1) / q[n];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
+  }
+  const T div = G[0][0] + G[1][1] + G[2][2];
+  const T two_rE = T(2) * rb[4 * g.N + id];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = a; d < 3; ++d) {
+      const T tau = c.ire * (G[a][d] + G[d][a] - (a == d ? T(2.0 / 3.0) * div : T(0)));
+      gbar[(long long)sym(a, d) * g.N + id] = two_rE * tau;
+    }
+}
+
+// Pass B: gather of all transposed-stencil and pointwise contributions.
+template <class T>
+__global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const T* __restrict__ q,
+                                                       const T* __restrict__ rb, const T* __restrict__ gbar,
+                                                       T* __restrict__ qbar) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.N) return;
+  int ijk[3];
+  coords(g, id, ijk);
+  const long long N = g.N;
+  const T half = T(0.5);
+
+  T q0[5], r0[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    q0[f] = q[f * N + id];
+    r0[f] = rb[f * N + id];
+  }
+  const T ir0 = T(1) / q0[0];
+  T u0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u0[a] = q0[a + 1] * ir0;
+  const T p0 = c.gm1 * (q0[4] - half * (q0[1] * u0[0] + q0[2] * u0[1] + q0[3] * u0[2]));
+  const T T0 = c.gm2 * p0 * ir0;
+
+  T qb[5] = {0, 0, 0, 0, 0};
+  T ub[3] = {0, 0, 0};
+  T pb = 0, Tb = 0;
+  T lap[3] = {0, 0, 0}, X[3] = {0, 0, 0};  // forward viscous pieces at this point
+
+  const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T qn[4][5], rn[4][5], un[4][3], pn[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const long long n = nb(g, id, ijk, d, offs[s]);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        qn[s][f] = q[f * N + n];
+        rn[s][f] = rb[f * N + n];
+      }
+      const T ir = T(1) / qn[s][0];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) un[s][a] = qn[s][a + 1] * ir;
+      pn[s] = c.gm1 * (qn[s][4] - half * (qn[s][1] * un[s][0] + qn[s][2] * un[s][1] + qn[s][3] * un[s][2]));
+    }
+    const T s1 = c.c1[d], s2 = c.c2[d];
+#define DN(expr_s) D1((expr_s(0)), (expr_s(1)), (expr_s(2)), (expr_s(3)), s1)
+    T sum_rq[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T acc = 0;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) acc += rn[s][f] * qn[s][f];
+      sum_rq[s] = acc;
+    }
+    const T dud = D1(un[0][d], un[1][d], un[2][d], un[3][d], s1);  // forward D_d u_d at this point
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
+      const T F = half * D1(rn[0][f], rn[1][f], rn[2][f], rn[3][f], s1);
+      qb[f] += F * u0[d];
+      ub[d] += F * q0[f];
+      // (2) u_d D_d q_f
+      qb[f] += half * D1(rn[0][f] * un[0][d], rn[1][f] * un[1][d], rn[2][f] * un[2][d], rn[3][f] * un[3][d], s1);
+      const T dq = D1(qn[0][f], qn[1][f], qn[2][f], qn[3][f], s1);
+      ub[d] -= half * r0[f] * dq;
+      // (3) q_f D_d u_d, pointwise part
+      qb[f] -= half * r0[f] * dud;
+    }
+    // (3) q_f D_d u_d, stencil part summed over f
+    ub[d] += half * D1(sum_rq[0], sum_rq[1], sum_rq[2], sum_rq[3], s1);
+    // (4) momentum pressure gradient D_d p
+    pb += D1(rn[0][d + 1], rn[1][d + 1], rn[2][d + 1], rn[3][d + 1], s1);
+    // (5) pressure work D_d(p u_d)
+    const T F5 = D1(rn[0][4], rn[1][4], rn[2][4], rn[3][4], s1);
+    pb += F5 * u0[d];
+    ub[d] += F5 * p0;
+    if (c.viscous) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
+        const T vb = D2(rn[0][a + 1] + rn[0][4] * un[0][a], rn[1][a + 1] + rn[1][4] * un[1][a],
+                        r0[a + 1] + r0[4] * u0[a], rn[2][a + 1] + rn[2][4] * un[2][a],
+                        rn[3][a + 1] + rn[3][4] * un[3][a], s2);
+        ub[a] += c.ire * vb;
+        if (a == d) ub[a] += c.ire * (T(1.0 / 3.0)) * vb;
+        // forward pieces of V_{m_a} at this point
+        const T l = D2(un[0][a], un[1][a], u0[a], un[2][a], un[3][a], s2);
+        lap[a] += l;
+        if (a == d) X[a] += l;
+        // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
+        const long long base = (long long)sym(a, d) * N;
+        ub[a] -= D1(gbar[base + nb(g, id, ijk, d, -2)], gbar[base + nb(g, id, ijk, d, -1)],
+                    gbar[base + nb(g, id, ijk, d, 1)], gbar[base + nb(g, id, ijk, d, 2)], s1);
+      }
+      // (8) heat flux
+      Tb += c.kap * D2(rn[0][4], rn[1][4], r0[4], rn[2][4], rn[3][4], s2);
+    }
+#undef DN
+  }
+
+  if (c.viscous) {
+    // Mixed derivatives on each coordinate plane (a, b).
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = a + 1; b < 3; ++b) {
+        T ua[4][4], ubb[4][4], va[4][4], vbb[4][4];
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia) {
+          const long long ida = nb(g, id, ijk, a, offs[ia]);
+          int ijka[3] = {ijk[0], ijk[1], ijk[2]};
+          const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+          int t = ijka[a] + offs[ia];
+          t += (t < 0) ? na : 0;
+          t -= (t >= na) ? na : 0;
+          ijka[a] = t;
+#pragma unroll
+          for (int ib = 0; ib < 4; ++ib) {
+            const long long n = nb(g, ida, ijka, b, offs[ib]);
+            const T ir = T(1) / q[n];
+            const T uan = q[(a + 1) * N + n] * ir, ubn = q[(b + 1) * N + n] * ir;
+            const T rE = rb[4 * N + n];
+            ua[ia][ib] = uan;
+            ubb[ia][ib] = ubn;
+            va[ia][ib] = rb[(a + 1) * N + n] + rE * uan;
+            vbb[ia][ib] = rb[(b + 1) * N + n] + rE * ubn;
+          }
+        }
+        T in_ub[4], in_ua[4], in_va[4], in_vb[4];
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia) {
+          in_ub[ia] = D1(ubb[ia][0], ubb[ia][1], ubb[ia][2], ubb[ia][3], c.c1[b]);
+          in_va[ia] = D1(va[ia][0], va[ia][1], va[ia][2], va[ia][3], c.c1[b]);
+        }
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          in_ua[ib] = D1(ua[0][ib], ua[1][ib], ua[2][ib], ua[3][ib], c.c1[a]);
+          in_vb[ib] = D1(vbb[0][ib], vbb[1][ib], vbb[2][ib], vbb[3][ib], c.c1[a]);
+        }
+        // forward: X_a += D_a D_b u_b, X_b += D_b D_a u_a
+        X[a] += D1(in_ub[0], in_ub[1], in_ub[2], in_ub[3], c.c1[a]);
+        X[b] += D1(in_ua[0], in_ua[1], in_ua[2], in_ua[3], c.c1[b]);
+        // adjoint: u_b += (1/(3 Re)) D_a D_b V_bar_a ; u_a += (1/(3 Re)) D_b D_a V_bar_b
+        ub[b] += c.ire * T(1.0 / 3.0) * D1(in_va[0], in_va[1], in_va[2], in_va[3], c.c1[a]);
+        ub[a] += c.ire * T(1.0 / 3.0) * D1(in_vb[0], in_vb[1], in_vb[2], in_vb[3], c.c1[b]);
+      }
+    // pointwise part of sum_a u_a V_{m_a}
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] += r0[4] * (c.ire * (lap[a] + X[a] * T(1.0 / 3.0)));
+  }
+
+  // Chain through the primitive variables at this point.
+  pb += c.gm2 * Tb * ir0;
+  qb[0] -= T0 * Tb * ir0;
+  qb[4] += c.gm1 * pb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qb[a + 1] -= half * c.gm1 * pb * u0[a];
+    ub[a] -= half * c.gm1 * pb * q0[a + 1];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qb[a + 1] += ub[a] * ir0;
+    qb[0] -= ub[a] * u0[a] * ir0;
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) qbar[f * N + id] += qb[f];
+}
+
+// Reversed RK stage: zeta += B q_bar ; r_bar = dt zeta ; zeta = A zeta.
+template <class T>
+__global__ void __launch_bounds__(kThreads) rk_adj(long long n5, T A, T B, T dt, const T* __restrict__ qbar,
+                                                   T* __restrict__ zeta, T* __restrict__ rbar) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  const T z = zeta[i] + B * qbar[i];
+  rbar[i] = dt * z;
+  zeta[i] = A * z;
+}
+
+// eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega.
+template <class T>
+__global__ void __launch_bounds__(kThreads) adj_vort(Grid g, Coef<T> c, T scale, const T* __restrict__ q,
+                                                     T* __restrict__ wbar) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.N) return;
+  int ijk[3];
+  coords(g, id, ijk);
+  T G[3][3];
+  const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T u[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const long long n = nb(g, id, ijk, d, offs[s]);
+      const T ir = T(1) / q[n];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
+  }
+  wbar[id] = scale * (G[2][1] - G[1][2]);
+  wbar[g.N + id] = scale * (G[0][2] - G[2][0]);
+  wbar[2 * g.N + id] = scale * (G[1][0] - G[0][1]);
+}
+
+// eps^S adjoint pass B: u_bar = curl_D(omega_bar), then through u = m / rho.
+template <class T>
+__global__ void __launch_bounds__(kThreads) adj_curl(Grid g, Coef<T> c, const T* __restrict__ q,
+                                                     const T* __restrict__ wbar, T* __restrict__ qbar) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.N) return;
+  int ijk[3];
+  coords(g, id, ijk);
+  const long long N = g.N;
+  auto d1w = [&](int comp, int d) {
+    const T* w = wbar + comp * N;
+    return D1(w[nb(g, id, ijk, d, -2)], w[nb(g, id, ijk, d, -1)], w[nb(g, id, ijk, d, 1)],
+              w[nb(g, id, ijk, d, 2)], c.c1[d]);
+  };
+  T ub[3];
+  ub[0] = d1w(2, 1) - d1w(1, 2);
+  ub[1] = d1w(0, 2) - d1w(2, 0);
+  ub[2] = d1w(1, 0) - d1w(0, 1);
+  const T ir = T(1) / q[id];
+  T rb = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qbar[(a + 1) * N + id] += ub[a] * ir;
+    rb -= ub[a] * q[(a + 1) * N + id] * ir * ir;
+  }
+  qbar[id] += rb;
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <class T>
+hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar, void* qbar,
+                                   void* work, hipStream_t st) {
+  const T* qq = static_cast<const T*>(q);
+  const T* rr = static_cast<const T*>(rbar);
+  T* gb = static_cast<T*>(work);
+  if (c.viscous) {
+    hipLaunchKernelGGL((adj_stress<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, gb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((adj_gather<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, gb,
+                     static_cast<T*>(qbar));
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_rk_stage_adjoint(const Grid& g, int stage, double dt, const void* qbar, void* zeta, void* rbar,
+                                   hipStream_t st) {
+  static const double kA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  const long long n5 = 5 * g.N;
+  hipLaunchKernelGGL((rk_adj<T>), dim3(blocks_for(n5)), dim3(kThreads), 0, st, n5, (T)kA[stage], (T)kB[stage],
+                     (T)dt, static_cast<const T*>(qbar), static_cast<T*>(zeta), static_cast<T*>(rbar));
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void* q, double eps_bar, void* qbar,
+                                    void* work, hipStream_t st) {
+  const T scale = (T)(eps_bar * 2.0 / ((double)g.N) * (double)c.ire);
+  hipLaunchKernelGGL((adj_vort<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, scale,
+                     static_cast<const T*>(q), static_cast<T*>(work));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((adj_curl<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, static_cast<const T*>(q),
+                     static_cast<const T*>(work), static_cast<T*>(qbar));
+  return hipGetLastError();
+}
+
+template hipError_t launch_residual_adjoint<double>(const Grid&, const Coef<double>&, const void*, const void*, void*,
+                                                    void*, hipStream_t);
+template hipError_t launch_residual_adjoint<float>(const Grid&, const Coef<float>&, const void*, const void*, void*,
+                                                   void*, hipStream_t);
+template hipError_t launch_rk_stage_adjoint<double>(const Grid&, int, double, const void*, void*, void*, hipStream_t);
+template hipError_t launch_rk_stage_adjoint<float>(const Grid&, int, double, const void*, void*, void*, hipStream_t);
+template hipError_t launch_integrals_adjoint<double>(const Grid&, const Coef<double>&, const void*, double, void*,
+                                                     void*, hipStream_t);
+template hipError_t launch_integrals_adjoint<float>(const Grid&, const Coef<float>&, const void*, double, void*,
+                                                    void*, hipStream_t);
+
+}  // namespace tgv

@@ -1,0 +1,84 @@
+// One stage of the two-register low-storage RK3 update (paper Sec. 3.1):
+//   Q~ <- A_i Q~ + dt R ;  Q <- Q + B_i Q~
+// with Williamson's coefficients.  A streaming kernel: each thread moves a
+// 16-byte-or-wider chunk of every array (8 consecutive elements), so all
+// loads and stores are full-width and coalesced; stage 0 never reads Q~.
+#include "tgv_device.h"
+#include "tgv_kernels.h"
+
+namespace tgv {
+
+namespace {
+
+constexpr int kElems = 8;  // elements per thread
+
+template <class T>
+struct alignas(sizeof(T) * kElems >= 16 ? 16 : sizeof(T) * kElems) Chunk {
+  T v[kElems];
+};
+
+template <class Tq, class Tqt, class Tr, class Ta, bool kFirst>
+__global__ void __launch_bounds__(256) rk_stage_kernel(long long n5, Ta A, Ta B, Ta dt, Tq* __restrict__ q,
+                                                       Tqt* __restrict__ qt, const Tr* __restrict__ r) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long base = t * kElems;
+  if (base + kElems <= n5) {
+    const Chunk<Tr> rv = reinterpret_cast<const Chunk<Tr>*>(r)[t];
+    Chunk<Tq> qv = reinterpret_cast<const Chunk<Tq>*>(q)[t];
+    Chunk<Tqt> tv;
+    if (!kFirst) tv = reinterpret_cast<const Chunk<Tqt>*>(qt)[t];
+#pragma unroll
+    for (int e = 0; e < kElems; ++e) {
+      const Ta rr = load_as<Ta>(rv.v[e]);
+      const Ta tn = kFirst ? dt * rr : A * load_as<Ta>(tv.v[e]) + dt * rr;
+      const Tqt ts = store_as<Tqt>(tn);
+      tv.v[e] = ts;
+      // Q is advanced with the stored (rounded) register value, as a
+      // separate Q~ array would be read back.
+      qv.v[e] = store_as<Tq>(load_as<Ta>(qv.v[e]) + B * load_as<Ta>(ts));
+    }
+    reinterpret_cast<Chunk<Tqt>*>(qt)[t] = tv;
+    reinterpret_cast<Chunk<Tq>*>(q)[t] = qv;
+  } else if (base < n5) {
+    for (long long e = base; e < n5; ++e) {
+      const Ta rr = load_as<Ta>(r[e]);
+      const Ta tn = kFirst ? dt * rr : A * load_as<Ta>(qt[e]) + dt * rr;
+      const Tqt ts = store_as<Tqt>(tn);
+      qt[e] = ts;
+      q[e] = store_as<Tq>(load_as<Ta>(q[e]) + B * load_as<Ta>(ts));
+    }
+  }
+}
+
+}  // namespace
+
+template <class Tq, class Tqt, class Tr, class Ta>
+hipError_t launch_rk_stage(const Grid& g, int stage, double dt, void* q, void* qt, const void* r,
+                           hipStream_t st) {
+  static const double kA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  const long long n5 = 5 * g.N;
+  const int threads = 256;
+  const long long chunks = (n5 + kElems - 1) / kElems;
+  const long long blocks = (chunks + threads - 1) / threads;
+  const Ta A = (Ta)kA[stage], B = (Ta)kB[stage], tdt = (Ta)dt;
+  if (stage == 0)
+    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, true>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                       n5, A, B, tdt, static_cast<Tq*>(q), static_cast<Tqt*>(qt), static_cast<const Tr*>(r));
+  else
+    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, false>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                       n5, A, B, tdt, static_cast<Tq*>(q), static_cast<Tqt*>(qt), static_cast<const Tr*>(r));
+  return hipGetLastError();
+}
+
+#define TGV_INST_RK(Tq, Tqt, Tr, Ta) \
+  template hipError_t launch_rk_stage<Tq, Tqt, Tr, Ta>(const Grid&, int, double, void*, void*, const void*, hipStream_t);
+TGV_INST_RK(double, double, double, double)
+TGV_INST_RK(double, double, float, double)
+TGV_INST_RK(float, float, float, double)
+TGV_INST_RK(float, float, float, float)
+TGV_INST_RK(float, float, f16, float)
+TGV_INST_RK(float, float, bf16, float)
+TGV_INST_RK(f16, f16, f16, float)
+
+}  // namespace tgv

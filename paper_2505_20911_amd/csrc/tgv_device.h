@@ -1,0 +1,128 @@
+// Device-side helpers shared by the HIP kernels of libtgv: storage types,
+// correctly rounded narrowing conversions, periodic index arithmetic and the
+// kernel-side parameter block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tgv {
+
+// bfloat16 storage: the upper 16 bits of an IEEE binary32.
+struct bf16 {
+  uint16_t bits;
+};
+
+using f16 = _Float16;
+
+__device__ __forceinline__ uint32_t f32_bits(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ float bits_f32(uint32_t u) { return __builtin_bit_cast(float, u); }
+
+// binary32 -> bfloat16, round to nearest even; NaN stays NaN (quietened).
+__device__ __forceinline__ bf16 f32_to_bf16(float x) {
+  uint32_t u = f32_bits(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40u)};
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+
+// binary64 -> binary32 rounded to odd (Boldo & Melquiond, "Emulation of FMA and
+// correctly rounded sums: proved algorithms using rounding to odd", IEEE TC 2008):
+// truncate toward zero, then set the last bit if the conversion was inexact.
+// A second rounding of the result to any format with at least two fewer
+// significand bits (binary16, bfloat16) is then the correctly rounded value.
+__device__ __forceinline__ float f64_to_f32_odd(double x) {
+  float f = (float)x;  // round to nearest even
+  double back = (double)f;
+  if (back == x || !(x == x)) return f;
+  uint32_t u = f32_bits(f);
+  // step toward zero if RNE rounded away from zero
+  if ((back > x && x > 0.0) || (back < x && x < 0.0)) u -= 1u;
+  return bits_f32(u | 1u);
+}
+
+// Storage conversions, templated on the storage type.
+template <class T>
+struct Conv;
+
+template <>
+struct Conv<double> {
+  __device__ __forceinline__ static double load_f64(double v) { return v; }
+  __device__ __forceinline__ static float load_f32(double v) { return (float)v; }
+  __device__ __forceinline__ static double from(double x) { return x; }
+  __device__ __forceinline__ static double from(float x) { return (double)x; }
+};
+
+template <>
+struct Conv<float> {
+  __device__ __forceinline__ static double load_f64(float v) { return (double)v; }
+  __device__ __forceinline__ static float load_f32(float v) { return v; }
+  __device__ __forceinline__ static float from(double x) { return (float)x; }
+  __device__ __forceinline__ static float from(float x) { return x; }
+};
+
+template <>
+struct Conv<f16> {
+  __device__ __forceinline__ static double load_f64(f16 v) { return (double)(float)v; }
+  __device__ __forceinline__ static float load_f32(f16 v) { return (float)v; }
+  __device__ __forceinline__ static f16 from(double x) { return (f16)f64_to_f32_odd(x); }
+  __device__ __forceinline__ static f16 from(float x) { return (f16)x; }
+};
+
+template <>
+struct Conv<bf16> {
+  __device__ __forceinline__ static double load_f64(bf16 v) {
+    return (double)bits_f32((uint32_t)v.bits << 16);
+  }
+  __device__ __forceinline__ static float load_f32(bf16 v) { return bits_f32((uint32_t)v.bits << 16); }
+  __device__ __forceinline__ static bf16 from(double x) { return f32_to_bf16(f64_to_f32_odd(x)); }
+  __device__ __forceinline__ static bf16 from(float x) { return f32_to_bf16(x); }
+};
+
+// Load a stored value into arithmetic type Tc.
+template <class Tc, class T>
+__device__ __forceinline__ Tc load_as(T v);
+template <>
+__device__ __forceinline__ double load_as<double, double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double load_as<double, float>(float v) { return (double)v; }
+template <>
+__device__ __forceinline__ double load_as<double, f16>(f16 v) { return (double)(float)v; }
+template <>
+__device__ __forceinline__ double load_as<double, bf16>(bf16 v) { return Conv<bf16>::load_f64(v); }
+template <>
+__device__ __forceinline__ float load_as<float, double>(double v) { return (float)v; }
+template <>
+__device__ __forceinline__ float load_as<float, float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float load_as<float, f16>(f16 v) { return (float)v; }
+template <>
+__device__ __forceinline__ float load_as<float, bf16>(bf16 v) { return Conv<bf16>::load_f32(v); }
+
+// Store an arithmetic value into storage type T (RNE, correctly rounded).
+template <class T, class Tc>
+__device__ __forceinline__ T store_as(Tc x) {
+  return Conv<T>::from(x);
+}
+
+// Grid description passed to kernels by value.
+struct Grid {
+  int nx, ny, nz;
+  long long N;       // nx * ny * nz
+  long long plane;   // nx * ny
+};
+
+// Physical coefficients in arithmetic type Tc (computed on the host in FP64,
+// rounded once).
+template <class Tc>
+struct Coef {
+  Tc c1[3];   // 1 / (12 h_d): first-derivative scale
+  Tc c2[3];   // 1 / (12 h_d^2): second-derivative scale
+  Tc gm1;     // gamma - 1
+  Tc gm2;     // gamma M^2
+  Tc ire;     // 1 / Re
+  Tc kap;     // 1 / ((gamma - 1) M^2 Pr Re)
+  int viscous;
+};
+
+}  // namespace tgv

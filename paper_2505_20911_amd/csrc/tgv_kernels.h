@@ -1,0 +1,42 @@
+// Host-side launchers of the libtgv kernels (one translation unit per kernel
+// family; the C-ABI layer in abi.hip validates arguments and dispatches here).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tgv_device.h"
+
+namespace tgv {
+
+template <class Tq>
+hipError_t launch_init(const Grid& g, const double L[3], double gamma, double mach, void* q,
+                       hipStream_t st);
+
+template <class Tq, class Tr, class Tc>
+hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, const void* q, void* r, hipStream_t st);
+
+template <class Tq, class Tqt, class Tr, class Ta>
+hipError_t launch_rk_stage(const Grid& g, int stage, double dt, void* q, void* qt, const void* r,
+                           hipStream_t st);
+
+// Number of first-pass blocks of the integrals reduction (workspace holds
+// 8 doubles per block).
+long long integrals_blocks(const Grid& g);
+
+template <class Tq>
+hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work,
+                            double* out8, hipStream_t st);
+
+template <class T>
+hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar,
+                                   void* qbar, void* work, hipStream_t st);
+
+template <class T>
+hipError_t launch_rk_stage_adjoint(const Grid& g, int stage, double dt, const void* qbar, void* zeta,
+                                   void* rbar, hipStream_t st);
+
+template <class T>
+hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void* q, double eps_bar,
+                                    void* qbar, void* work, hipStream_t st);
+
+}  // namespace tgv

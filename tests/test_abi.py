@@ -1,0 +1,104 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/tgv.h declares, and rejects bad arguments on the host
+(validation runs before any HIP call) with the documented codes and a message."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2505_20911_amd import tgv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tgv.h")
+
+NS_ERR_ARG, NS_ERR_DTYPE, NS_ERR_SHAPE, NS_ERR_ALIGN = -1, -2, -3, -4
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char\s*\*|void)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tgv.load()
+    names = declared_functions()
+    assert len(names) >= 12, names
+    for name in names:
+        assert hasattr(lib, name), f"libtgv.so does not export {name}"
+    assert set(names) == set(tgv._EXPORTS), "binding and header disagree"
+
+
+def test_abi_version():
+    assert tgv.tgv_abi_version() == 1
+
+
+def _call_residual(params, prec, q=0x1000, r=0x2000):
+    lib = tgv.load()
+    return lib.ns_residual(ctypes.byref(params.c()), ctypes.byref(prec.c()), ctypes.c_void_p(q),
+                           ctypes.c_void_p(r), None)
+
+
+@pytest.mark.parametrize("n", [(4, 8, 8), (8, 4, 8), (8, 8, 2), (0, 8, 8)])
+def test_rejects_grids_below_stencil_width(n):
+    assert _call_residual(tgv.Params(n=n), tgv.PRESETS["DP"]) == NS_ERR_SHAPE
+    assert "< 5" in tgv.ns_last_error()
+
+
+def test_rejects_unsupported_precision_forms():
+    bad = [tgv.Prec(tgv.f16, tgv.f64, tgv.f64, tgv.f64), tgv.Prec(tgv.f64, tgv.f64, tgv.f64, tgv.f16),
+           tgv.Prec(tgv.f32, tgv.f32, tgv.f32, tgv.f16), tgv.Prec(tgv.bf16, tgv.bf16, tgv.bf16, tgv.f32)]
+    for prec in bad:
+        assert _call_residual(tgv.Params(n=(8, 8, 8)), prec) == NS_ERR_DTYPE
+        assert "unsupported precision form" in tgv.ns_last_error()
+
+
+def test_rejects_null_and_misaligned_and_aliased_pointers():
+    p, prec = tgv.Params(n=(8, 8, 8)), tgv.PRESETS["DP"]
+    lib = tgv.load()
+    assert lib.ns_residual(ctypes.byref(p.c()), ctypes.byref(prec.c()), None, ctypes.c_void_p(0x2000),
+                           None) == NS_ERR_ARG
+    assert "q is NULL" in tgv.ns_last_error()
+    assert _call_residual(p, prec, q=0x1008) == NS_ERR_ALIGN
+    assert _call_residual(p, prec, q=0x1000, r=0x1000) == NS_ERR_ARG
+    assert lib.ns_residual(None, ctypes.byref(prec.c()), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                           None) == NS_ERR_ARG
+
+
+def test_rejects_bad_scalars():
+    lib = tgv.load()
+    prec = tgv.PRESETS["DP"]
+    for kw in ({"gamma": 1.0}, {"mach": 0.0}, {"reynolds": -1.0}, {"prandtl": float("nan")},
+               {"viscous": 2}, {"L": (6.28, 0.0, 6.28)}):
+        p = tgv.Params(n=(8, 8, 8), **kw)
+        assert _call_residual(p, prec) == NS_ERR_ARG, kw
+    p = tgv.Params(n=(8, 8, 8))
+    for stage in (-1, 3):
+        assert lib.rk_stage(ctypes.byref(p.c()), ctypes.byref(prec.c()), stage, 0.1, ctypes.c_void_p(0x1000),
+                            ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None) == NS_ERR_ARG
+    assert lib.rk_stage(ctypes.byref(p.c()), ctypes.byref(prec.c()), 0, float("inf"), ctypes.c_void_p(0x1000),
+                        ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None) == NS_ERR_ARG
+
+
+def test_adjoint_forms_and_workspace_sizes():
+    p = tgv.Params(n=(8, 10, 12))
+    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["DP"]) == 6 * p.N * 8
+    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["SP"]) == 6 * p.N * 4
+    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["HPSP"]) == 0  # unsupported form
+    assert tgv.flow_integrals_adjoint_workspace_bytes(p, tgv.PRESETS["DP"]) == 3 * p.N * 8
+    assert tgv.flow_integrals_workspace_bytes(p) >= 8 * 8
+    lib = tgv.load()
+    rc = lib.ns_residual_adjoint(ctypes.byref(p.c()), ctypes.byref(tgv.PRESETS["HPSP"].c()),
+                                 ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000),
+                                 ctypes.c_void_p(0x4000), None)
+    assert rc == NS_ERR_DTYPE
+
+
+def test_python_binding_refuses_host_tensors():
+    import torch
+    p = tgv.Params(n=(8, 8, 8))
+    q = torch.zeros(p.shape, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        tgv.ns_residual(p, tgv.PRESETS["DP"], q, q.clone())
