@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build", "libtgv")
 LIB = os.path.join(PKG, "libtgv.so")
 ARCH = os.environ.get("TGV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.hip", "init.hip", "residual.hip", "rk_stage.hip", "integrals.hip", "adjoint.hip"]
+SOURCES = ["abi.hip", "init.hip", "residual_tiled.hip", "rk_stage.hip", "integrals.hip", "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
