@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--forms", default=",".join(ALL_FORMS))
+    ap.add_argument("--paths", default="fused,split", help="fused and/or split residual + stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the oracle sample")
     return ap.parse_args()
@@ -42,14 +43,17 @@ def nbytes(dtype):
     return torch.empty((), dtype=dtype).element_size()
 
 
-def time_form(form, n, steps, warmup, dt):
+def time_form(form, n, steps, warmup, dt, fused):
+    """Time `steps` full RK3 steps.  HIP events are recorded on the launch
+    stream around every kernel launch of the step, giving each kernel's
+    average duration inside the timed region."""
     import torch
     from paper_2505_20911_amd import tgv
     from paper_2505_20911_amd.solver import TGVSolver
 
     prec = tgv.PRESETS[form]
     p = tgv.Params(n=(n, n, n))
-    s = TGVSolver(p, prec)
+    s = TGVSolver(p, prec, fused=fused)
     s.init()
     every = 10
     hist = torch.empty((steps // every + 2, 8), dtype=torch.float64, device="cuda")
@@ -57,7 +61,7 @@ def time_form(form, n, steps, warmup, dt):
         s.step(dt)
     torch.cuda.synchronize()
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    res_ev, rk_ev = [], []
+    k_ev = []  # (start, end, kind, stage)
     t_start, t_end = ev(), ev()
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
@@ -68,37 +72,52 @@ def time_form(form, n, steps, warmup, dt):
             s.integrals(hist[row])
             row += 1
         for i in range(3):
-            a, b, c = ev(), ev(), ev()
-            a.record(stream)
-            tgv.ns_residual(p, prec, s.q, s.r)
-            b.record(stream)
-            tgv.rk_stage(p, prec, i, dt, s.q, s.qt, s.r)
-            c.record(stream)
-            res_ev.append((a, b))
-            rk_ev.append((b, c, i))
+            if fused:
+                a, b = ev(), ev()
+                a.record(stream)
+                s.stage(i, dt)
+                b.record(stream)
+                k_ev.append((a, b, "fused", i))
+            else:
+                a, b, c = ev(), ev(), ev()
+                a.record(stream)
+                tgv.ns_residual(p, prec, s.q, s.r)
+                b.record(stream)
+                tgv.rk_stage(p, prec, i, dt, s.q, s.qt, s.r)
+                c.record(stream)
+                k_ev.append((a, b, "residual", i))
+                k_ev.append((b, c, "rk_stage", i))
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = t_start.elapsed_time(t_end)
-    res_ms = [a.elapsed_time(b) for a, b in res_ev]
-    rk_ms = [(b.elapsed_time(c), i) for b, c, i in rk_ev]
-    finite = bool(torch.isfinite(hist[:row]).all())
     N = p.N
     bq, bqt, br = nbytes(prec.q), nbytes(prec.qt), nbytes(prec.r)
-    res_bytes = 5 * N * (bq + br)
-    rk_bytes = {0: 5 * N * (br + 2 * bq + bqt), 1: 5 * N * (br + 2 * bq + 2 * bqt), 2: 5 * N * (br + 2 * bq + 2 * bqt)}
-    res_avg = sum(res_ms) / len(res_ms)
-    rk_avg = sum(t for t, _ in rk_ms) / len(rk_ms)
-    rk_gbs = sum(rk_bytes[i] / (t * 1e-3) for t, i in rk_ms) / len(rk_ms) / 1e9
+    # algorithmic bytes per launch, by kernel and stage
+    algo = {
+        "residual": lambda i: 5 * N * (bq + br),
+        "rk_stage": lambda i: 5 * N * (br + 2 * bq + (bqt if i == 0 else 2 * bqt)),
+        "fused": lambda i: 5 * N * (2 * bq + (bqt if i == 0 else 2 * bqt)),
+    }
+    kern = {}
+    for a, b, kind, i in k_ev:
+        ms = a.elapsed_time(b)
+        d = kern.setdefault(kind, {"ms": [], "bytes": []})
+        d["ms"].append(ms)
+        d["bytes"].append(algo[kind](i))
+    kernels = {}
+    for kind, d in kern.items():
+        avg_ms = sum(d["ms"]) / len(d["ms"])
+        avg_b = sum(d["bytes"]) / len(d["bytes"])
+        kernels[kind] = {"avg_ms": avg_ms, "bytes_per_launch": avg_b,
+                         "gbs": avg_b / (avg_ms * 1e-3) / 1e9, "launches": len(d["ms"])}
+    finite = bool(torch.isfinite(hist[:row]).all())
     out = {
+        "path": "fused" if fused else "split",
         "mpt_stage_per_s": N * 3 * steps / (wall * 1e6),
         "ms_per_step": 1e3 * wall / steps,
         "gpu_ms_per_step": gpu_ms / steps,
-        "residual_ms": res_avg,
-        "residual_bytes_per_launch": res_bytes,
-        "residual_gbs": res_bytes / (res_avg * 1e-3) / 1e9,
-        "rk_stage_ms": rk_avg,
-        "rk_stage_gbs": rk_gbs,
+        "kernels": kernels,
         "finite": finite,
         "K_first": float(hist[0, 0]),
     }
@@ -137,17 +156,22 @@ def main():
     n = args.n
     dt = 3.7e-3 * 32 / n
     forms = [f for f in args.forms.split(",") if f]
+    paths = [x for x in args.paths.split(",") if x]
     results = {}
     for f in forms:
-        print(f"[bench] {f} {n}^3: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-        results[f] = time_form(f, n, args.steps, args.warmup, dt)
-        print(f"[bench] {f}: {results[f]['mpt_stage_per_s']:.0f} Mpt.stage/s, residual "
-              f"{results[f]['residual_ms']:.3f} ms ({results[f]['residual_gbs']:.0f} GB/s)",
-              file=sys.stderr, flush=True)
-    head = results.get("DP") or results[forms[0]]
-    head_form = "DP" if "DP" in results else forms[0]
-    for f, r in results.items():
-        r["speedup_vs_DP"] = r["mpt_stage_per_s"] / results["DP"]["mpt_stage_per_s"] if "DP" in results else None
+        for path in paths:
+            key = f if path == "fused" else f + "/split"
+            print(f"[bench] {key} {n}^3: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+            results[key] = time_form(f, n, args.steps, args.warmup, dt, path == "fused")
+            r = results[key]
+            ks = ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['gbs']:.0f} GB/s" for k, v in r["kernels"].items())
+            print(f"[bench] {key}: {r['mpt_stage_per_s']:.0f} Mpt.stage/s ({ks})", file=sys.stderr, flush=True)
+    head_key = "DP" if "DP" in results else next(iter(results))
+    head = results[head_key]
+    for key, r in results.items():
+        r["speedup_vs_DP"] = r["mpt_stage_per_s"] / head["mpt_stage_per_s"]
+    kname = "fused" if head["path"] == "fused" else "residual"
+    hk = head["kernels"][kname]
     line = {
         "metric": METRIC,
         "value": head["mpt_stage_per_s"],
@@ -159,16 +183,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head_form == "DP" else head_form,
+        "dtype": "f64" if head_key.startswith("DP") else head_key,
         "data": "synthetic",
-        "config": {"workload": f"Taylor-Green vortex, periodic (2pi)^3, {n}^3 points, Re=1600, M=0.1, "
-                               f"{head_form} form, RK3 dt={dt:.6g}, integrals every 10 steps",
-                   "grid": [n, n, n], "form": head_form},
-        "roofline": {"bound": "hbm", "kernel": "ns_residual",
-                     "achieved": head["residual_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["residual_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": head["residual_bytes_per_launch"],
-                     "avg_launch_ms": head["residual_ms"]},
+        "config": {"workload": f"Taylor-Green vortex, periodic (2pi)^3, {n}^3 points, Re=1600, M=0.1, Pr=0.71, "
+                               f"FP64 (DP form), RK3 dt={dt:.6g}, {head['path']} residual+stage, "
+                               f"integrals every 10 steps",
+                   "grid": [n, n, n], "form": head_key, "path": head["path"]},
+        "roofline": {"bound": "hbm", "kernel": "ns_residual_rk_stage" if kname == "fused" else "ns_residual",
+                     "achieved": hk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hk["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"]},
         "forms": results,
     }
     if not args.no_cpu_baseline:

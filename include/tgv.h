@@ -108,6 +108,17 @@ int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q,
 int rk_stage(const ns_params_t* params, const ns_prec_t* prec, int stage, double dt, void* q,
              void* qt, const void* r, void* stream);
 
+/* Residual and RK stage in one pass over the grid (the two calls above fused,
+ * so R never goes through memory):
+ *   Q~ <- A_i Q~ + dt R(q_in) ;  q_out <- q_in + B_i Q~
+ * with R rounded to prec->r exactly as ns_residual would store it and rk_stage
+ * read it back, so the result equals ns_residual followed by rk_stage.
+ * q_in (prec->q) is read, q_out (prec->q) written, qt (prec->qt) updated in
+ * place (not read at stage 0).  q_in, q_out and qt must be distinct arrays:
+ * every point's stencil reads q_in around it while q_out is written. */
+int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int stage, double dt,
+                         const void* q_in, void* q_out, void* qt, void* stream);
+
 /* Bytes of device workspace flow_integrals() needs for this grid. */
 size_t flow_integrals_workspace_bytes(const ns_params_t* params);
 

@@ -2,7 +2,9 @@
 
 Each .hip source is compiled to an object with hipcc (in parallel), then the
 objects are linked into paper_2505_20911_amd/libtgv.so.  Packed-FP32 VALU
-instructions are disabled for all device code.
+instructions are disabled for all device code, and multiply-add contraction is
+limited to single source expressions (-ffp-contract=on) so that the same
+expression rounds identically wherever it is inlined.
 """
 from __future__ import annotations
 
@@ -26,6 +28,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are contracted only within one source expression, so a
+    # computation rounds the same way in every kernel and unrolled copy
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -200,6 +200,59 @@ int rk_stage(const ns_params_t* params, const ns_prec_t* prec, int stage, double
   return hip_status(e, "rk_stage");
 }
 
+int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int stage, double dt, const void* q_in,
+                         void* q_out, void* qt, void* stream) {
+  tgv::Grid g;
+  Form f;
+  int rc = check_params(params, &g);
+  if (rc) return rc;
+  if ((rc = check_prec(prec, &f))) return rc;
+  if (stage < 0 || stage > 2) return fail(NS_ERR_ARG, "stage must be 0, 1 or 2");
+  if (!std::isfinite(dt)) return fail(NS_ERR_ARG, "dt must be finite");
+  if ((rc = check_ptr(q_in, "q_in")) || (rc = check_ptr(q_out, "q_out")) || (rc = check_ptr(qt, "qt"))) return rc;
+  if (q_in == q_out || q_in == qt || q_out == qt) return fail(NS_ERR_ARG, "q_in, q_out and qt must be distinct arrays");
+  hipStream_t st = as_stream(stream);
+  hipError_t e = hipSuccess;
+  using tgv::bf16;
+  using tgv::f16;
+  switch (f) {
+    case DP:
+      e = tgv::launch_residual_rk<double, double, double, double, double>(g, make_coef<double>(params), stage, dt,
+                                                                          q_in, q_out, qt, st);
+      break;
+    case SPDP:
+      e = tgv::launch_residual_rk<double, double, float, float, double>(g, make_coef<float>(params), stage, dt, q_in,
+                                                                        q_out, qt, st);
+      break;
+    case SPDP_C64:
+      e = tgv::launch_residual_rk<double, double, float, double, double>(g, make_coef<double>(params), stage, dt,
+                                                                         q_in, q_out, qt, st);
+      break;
+    case SP_DPC:
+      e = tgv::launch_residual_rk<float, float, float, double, double>(g, make_coef<double>(params), stage, dt, q_in,
+                                                                       q_out, qt, st);
+      break;
+    case SP:
+      e = tgv::launch_residual_rk<float, float, float, float, float>(g, make_coef<float>(params), stage, dt, q_in,
+                                                                     q_out, qt, st);
+      break;
+    case HPSP:
+      e = tgv::launch_residual_rk<float, float, f16, float, float>(g, make_coef<float>(params), stage, dt, q_in, q_out,
+                                                                   qt, st);
+      break;
+    case HPSP_BF16:
+      e = tgv::launch_residual_rk<float, float, bf16, float, float>(g, make_coef<float>(params), stage, dt, q_in,
+                                                                    q_out, qt, st);
+      break;
+    case HP:
+      e = tgv::launch_residual_rk<f16, f16, f16, float, float>(g, make_coef<float>(params), stage, dt, q_in, q_out, qt,
+                                                               st);
+      break;
+    default: break;
+  }
+  return hip_status(e, "ns_residual_rk_stage");
+}
+
 size_t flow_integrals_workspace_bytes(const ns_params_t* params) {
   tgv::Grid g;
   if (check_params(params, &g)) return 0;

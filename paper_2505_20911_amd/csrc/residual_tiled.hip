@@ -2,20 +2,22 @@
 // scheme and Blaisdell split form, Sec. 3.1 state vector and residual),
 // tiled for CDNA4.
 //
-// Work decomposition.  A 256-thread block owns a 64 x 4 tile of (x, y)
-// columns and marches along z over a chunk of planes.  Per plane p it
-//   1. loads Q on the tile plus a 2-point halo (68 x 8 points, coalesced
-//      along x), converts to the arithmetic type Tc and derives the
-//      primitive variables once per point into one LDS plane of 10 fields
-//      (rho, m1, m2, m3, rho E, u, v, w, p, T);
+// Work decomposition.  A block of 64 x TY threads owns a 64 x TY tile of
+// (x, y) columns and marches along z over a chunk of planes.  Per plane p it
+//   1. loads Q on the tile plus a 2-point halo (coalesced along x), converts
+//      to the arithmetic type Tc and derives the primitive variables once per
+//      point into one LDS plane of 10 fields (rho, m1, m2, m3, rho E, u, v, w,
+//      p, T);
 //   2. evaluates every x- and y-derivative term of R at its own column from
 //      LDS (split convective fluxes, pressure, viscous and heat-flux terms,
-//      the x-y mixed derivatives) and keeps the result, plus the six
-//      in-plane velocity gradients, in registers;
+//      the x-y mixed derivatives, and the part of the viscous work tau : grad u
+//      made of in-plane gradients only) and parks that partial R in a
+//      thread-private LDS ring; it keeps three gradient combinations in
+//      registers: D_x w, D_y w and D_x u + D_y v;
 //   3. emits R for plane p - 2: its z-derivative terms come from a 5-plane
-//      register window of the 10 fields, the z-mixed derivatives are
-//      z-differences of the stored in-plane gradients, and the viscous work
-//      tau : grad u needs all nine gradients at once.
+//      register window of the 10 fields; the z-mixed derivatives of the
+//      viscous term are z-differences of the three stored combinations, which
+//      are also all that the remaining (in-plane x z) part of tau : grad u needs.
 // The z loop is unrolled by the window length (5) so that the window rotates
 // by renaming, not by register moves.  The next plane's loads are issued
 // before the current plane's arithmetic.  Tiles are ordered so that
@@ -30,6 +32,8 @@
 //   m_a, a!=d:  1/2 m_a u_d
 //   m_d:        1/2 m_d u_d + p          (split flux plus pressure gradient)
 //   rho E:      (1/2 rho E + p) u_d      (split flux plus pressure work)
+#include <type_traits>
+
 #include "tgv_device.h"
 #include "tgv_kernels.h"
 
@@ -37,23 +41,37 @@ namespace tgv {
 
 namespace {
 
-constexpr int TX = 64, TY = 4, NT = TX * TY;
+#ifndef TGV_TILE_Y
+#define TGV_TILE_Y 4
+#endif
+#ifndef TGV_MIN_WAVES
+#define TGV_MIN_WAVES 1
+#endif
+#ifndef TGV_EARLY_EMIT
+#define TGV_EARLY_EMIT 0
+#endif
+constexpr int TX = 64, TY = TGV_TILE_Y, NT = TX * TY;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
 constexpr int NF = 10;
 enum { F_RHO = 0, F_M = 1, F_E = 4, F_U = 5, F_P = 8, F_T = 9 };
 constexpr int KZ = 64;  // planes per block
 
+// Fields kept per plane in the z-window: the conserved variables and 1/rho;
+// u, v, w, p and T are re-derived from them where the z-stencils need them.
+constexpr int NW = 6;
+enum { W_IR = 5 };
+
 template <class Tc>
 struct Ctx {
-  // z-window: the 10 fields of this column at the last 5 planes
-  Tc W[5][NF];
-  // in-plane velocity gradients G[a][d] (d = x, y) per plane slot:
-  // 0: u_x 1: u_y 2: v_x 3: v_y 4: w_x 5: w_y
-  Tc GI[5][6];
-  // in-plane part of R per plane slot
-  Tc RI[5][5];
+  // z-window: rho, m1, m2, m3, rho E, 1/rho of this column at the last 5 planes
+  Tc W[5][NW];
+  // per plane slot: 0: D_x w, 1: D_y w, 2: D_x u + D_y v
+  Tc A[5][3];
 };
+
+// Thread-private ring of in-plane partial residuals in LDS: [3 slots][5][NT].
+constexpr int RI_SLOTS = 3;
 
 template <class Tc>
 __device__ __forceinline__ Tc S1(Tc m2, Tc m1, Tc p1, Tc p2) {
@@ -90,11 +108,23 @@ struct LdsNb {
   }
 };
 
+// The 10 fields of one z-window slot, re-derived from (rho, m, rho E, 1/rho)
+// exactly as primitives() derives them.
+template <class Tc>
+__device__ __forceinline__ Tc derived(const Tc* w, int f, const Coef<Tc>& c) {
+  if (f < 5) return w[f];
+  if (f < F_P) return w[f - 4] * w[W_IR];
+  const Tc u = w[1] * w[W_IR], v = w[2] * w[W_IR], x = w[3] * w[W_IR];
+  const Tc p = c.gm1 * (w[4] - Tc(0.5) * (w[1] * u + w[2] * v + w[3] * x));
+  return f == F_P ? p : c.gm2 * p * w[W_IR];
+}
+
 template <class Tc, int A, int B, int C, int D>
 struct WinNb {
-  const Tc (&W)[5][NF];
+  const Tc (&W)[5][NW];
+  const Coef<Tc>& c;
   __device__ __forceinline__ Tc operator()(int f, int s) const {
-    return s == 0 ? W[A][f] : s == 1 ? W[B][f] : s == 2 ? W[C][f] : W[D][f];
+    return derived(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
   }
 };
 
@@ -163,17 +193,36 @@ struct Kernel {
   Grid g;
   Coef<Tc> c;
   const Tq* __restrict__ q;
-  Tr* __restrict__ r;
+  Tr* __restrict__ r;  // residual output (residual-only launch)
+};
+
+// Extra arguments of the fused residual + RK stage launch.
+template <class Tq, class Tqt, class Ta>
+struct RkArgs {
+  Tq* __restrict__ q_out;
+  Tqt* __restrict__ qt;
+  Ta A, B, dt;
+  int first;  // stage 0: the register is not read
 };
 
 // One z-step with the newest plane in window slot PH.
-template <class Tq, class Tr, class Tc, int PH>
-__device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, Ctx<Tc>& cx, Tc* lds, Tc (&nxt)[LOADS][5],
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int PH>
+__device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, Ctx<Tc>& cx,
+                                      Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k, Tc (&nxt)[LOADS][5],
                                       const long long (&off)[LOADS], int p, int kout_lo, int kout_hi,
                                       bool col_valid, long long col_off, int p_last) {
   const int tid = threadIdx.x;
   const Grid& g = K.g;
   const Coef<Tc>& c = K.c;
+  // register values of the plane emitted in this step, requested early
+  const int k = p - 2;
+  const bool emit = k >= kout_lo && k < kout_hi;
+  Tqt qt_k[5] = {Tqt(), Tqt(), Tqt(), Tqt(), Tqt()};
+  if (FUSED && emit && col_valid && !rk.first) {
+    const long long id = (long long)k * g.plane + col_off;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qt_k[f] = rk.qt[f * g.N + id];
+  }
   // 1. primitives of the prefetched plane into LDS
 #pragma unroll
   for (int l = 0; l < LOADS; ++l) {
@@ -204,20 +253,28 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, Ctx<Tc>& cx, 
   // 2. in-plane terms of plane p at this column
   const int tx = tid % TX, ty = tid / TX;
   const int own = (ty + 2) * HX + (tx + 2);
+  Tc c0[NF];
 #pragma unroll
-  for (int k = 0; k < NF; ++k) cx.W[PH][k] = lds[k * NPL + own];
-  const Tc* c0 = cx.W[PH];
+  for (int k = 0; k < NF; ++k) c0[k] = lds[k * NPL + own];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) cx.W[PH][k] = c0[k];
+  cx.W[PH][W_IR] = Tc(1) / c0[F_RHO];
   Tc R[5] = {0, 0, 0, 0, 0};
   {
-    Tc G[3] = {0, 0, 0};
-    direction_terms<Tc, 0>(LdsNb<Tc, 1>{lds, own}, c0, c, c.c1[0], c.c2[0], R, G);
-    cx.GI[PH][0] = G[0];
-    cx.GI[PH][2] = G[1];
-    cx.GI[PH][4] = G[2];
-    direction_terms<Tc, 1>(LdsNb<Tc, HX>{lds, own}, c0, c, c.c1[1], c.c2[1], R, G);
-    cx.GI[PH][1] = G[0];
-    cx.GI[PH][3] = G[1];
-    cx.GI[PH][5] = G[2];
+    Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
+    direction_terms<Tc, 0>(LdsNb<Tc, 1>{lds, own}, c0, c, c.c1[0], c.c2[0], R, Gx);
+    direction_terms<Tc, 1>(LdsNb<Tc, HX>{lds, own}, c0, c, c.c1[1], c.c2[1], R, Gy);
+    cx.A[PH][0] = Gx[2];
+    cx.A[PH][1] = Gy[2];
+    cx.A[PH][2] = Gx[0] + Gy[1];
+    if (c.viscous) {
+      // in-plane part of tau : grad u (times Re):
+      //   sum_{a, d in x,y} G_ad^2 + G_xx^2 + G_yy^2 + 2 G_xy G_yx - 2/3 (G_xx + G_yy)^2
+      const Tc a3 = cx.A[PH][2];
+      const Tc sq = Gx[0] * Gx[0] + Gx[1] * Gx[1] + Gx[2] * Gx[2] + Gy[0] * Gy[0] + Gy[1] * Gy[1] + Gy[2] * Gy[2];
+      const Tc cr = Gx[0] * Gx[0] + Gy[1] * Gy[1] + Tc(2) * Gy[0] * Gx[1];
+      R[4] += c.ire * (sq + cr - Tc(2.0 / 3.0) * a3 * a3);
+    }
   }
   if (c.viscous) {
     // x-y mixed derivatives: X_x += D_x D_y v, X_y += D_y D_x u (corners of the 5 x 5 patch)
@@ -242,51 +299,82 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, Ctx<Tc>& cx, 
     R[2] += my;
     R[4] += c0[F_U] * mx + c0[F_U + 1] * my;
   }
+  {
+    Tc* ri = lds_ri + (ri_slot_p * 5) * NT + tid;
 #pragma unroll
-  for (int f = 0; f < 5; ++f) cx.RI[PH][f] = R[f];
+    for (int f = 0; f < 5; ++f) ri[f * NT] = R[f];
+  }
+#if !TGV_EARLY_EMIT
   __syncthreads();
+#endif
 
   // 3. emit plane k = p - 2 (window slots: k-2 .. k+2)
-  const int k = p - 2;
-  if (k >= kout_lo && k < kout_hi) {
+  if (emit) {
     constexpr int KM2 = (PH + 1) % 5, KM1 = (PH + 2) % 5, K0 = (PH + 3) % 5, KP1 = (PH + 4) % 5, KP2 = PH;
-    Tc Rz[5] = {cx.RI[K0][0], cx.RI[K0][1], cx.RI[K0][2], cx.RI[K0][3], cx.RI[K0][4]};
+    Tc Rz[5];
+    {
+      const Tc* ri = lds_ri + (ri_slot_k * 5) * NT + tid;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) Rz[f] = ri[f * NT];
+    }
     Tc Gz[3] = {0, 0, 0};
-    direction_terms<Tc, 2>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W}, cx.W[K0], c, c.c1[2], c.c2[2], Rz, Gz);
+    Tc ck[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) ck[f] = derived(cx.W[K0], f, c);
+    direction_terms<Tc, 2>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W, c}, ck, c, c.c1[2], c.c2[2], Rz, Gz);
     if (c.viscous) {
-      const Tc* u0 = cx.W[K0] + F_U;
-      // z-mixed: X_x += D_z(w_x), X_y += D_z(w_y), X_z += D_z(u_x) + D_z(v_y)
+      const Tc* u0 = ck + F_U;
+      // z-mixed: X_x += D_z(w_x), X_y += D_z(w_y), X_z += D_z(u_x + v_y)
       const Tc cz = c.c1[2] * c.ire * Tc(1.0 / 3.0);
-      const Tc mx = cz * S1(cx.GI[KM2][4], cx.GI[KM1][4], cx.GI[KP1][4], cx.GI[KP2][4]);
-      const Tc my = cz * S1(cx.GI[KM2][5], cx.GI[KM1][5], cx.GI[KP1][5], cx.GI[KP2][5]);
-      const Tc mz = cz * (S1(cx.GI[KM2][0], cx.GI[KM1][0], cx.GI[KP1][0], cx.GI[KP2][0]) +
-                          S1(cx.GI[KM2][3], cx.GI[KM1][3], cx.GI[KP1][3], cx.GI[KP2][3]));
+      const Tc mx = cz * S1(cx.A[KM2][0], cx.A[KM1][0], cx.A[KP1][0], cx.A[KP2][0]);
+      const Tc my = cz * S1(cx.A[KM2][1], cx.A[KM1][1], cx.A[KP1][1], cx.A[KP2][1]);
+      const Tc mz = cz * S1(cx.A[KM2][2], cx.A[KM1][2], cx.A[KP1][2], cx.A[KP2][2]);
       Rz[1] += mx;
       Rz[2] += my;
       Rz[3] += mz;
       Rz[4] += u0[0] * mx + u0[1] * my + u0[2] * mz;
-      // viscous work tau : grad u = (1/Re)[sum G_ad^2 + sum G_ad G_da - 2/3 div^2]
-      const Tc G00 = cx.GI[K0][0], G01 = cx.GI[K0][1], G02 = Gz[0];
-      const Tc G10 = cx.GI[K0][2], G11 = cx.GI[K0][3], G12 = Gz[1];
-      const Tc G20 = cx.GI[K0][4], G21 = cx.GI[K0][5], G22 = Gz[2];
-      const Tc div = G00 + G11 + G22;
-      const Tc sq = G00 * G00 + G01 * G01 + G02 * G02 + G10 * G10 + G11 * G11 + G12 * G12 + G20 * G20 +
-                    G21 * G21 + G22 * G22;
-      const Tc cr = G00 * G00 + G11 * G11 + G22 * G22 + Tc(2) * (G01 * G10 + G02 * G20 + G12 * G21);
-      Rz[4] += c.ire * (sq + cr - Tc(2.0 / 3.0) * div * div);
+      // remaining part of tau : grad u (times Re), with G_az = Gz[a]:
+      //   sum_a G_az^2 + 2 (G_xz G_zx + G_yz G_zy) + G_zz^2 - 2/3 (2 (G_xx + G_yy) G_zz + G_zz^2)
+      const Tc a1 = cx.A[K0][0], a2 = cx.A[K0][1], a3 = cx.A[K0][2];
+      const Tc sq = Gz[0] * Gz[0] + Gz[1] * Gz[1] + Gz[2] * Gz[2];
+      const Tc cr = Tc(2) * (Gz[0] * a1 + Gz[1] * a2) + Gz[2] * Gz[2];
+      Rz[4] += c.ire * (sq + cr - Tc(2.0 / 3.0) * (Tc(2) * a3 + Gz[2]) * Gz[2]);
     }
     if (col_valid) {
       const long long id = (long long)k * g.plane + col_off;
+      if (!FUSED) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) K.r[f * g.N + id] = store_as<Tr>(Rz[f]);
+        for (int f = 0; f < 5; ++f) K.r[f * g.N + id] = store_as<Tr>(Rz[f]);
+      } else {
+        // Q~ <- A Q~ + dt R ; Q_out <- Q_in + B Q~, with R rounded to its
+        // storage type as a stored residual would be.  Q_in at this point is
+        // the window's centre when the arithmetic type is the storage type
+        // (exact), else it is re-read in its storage type.
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          const Ta rr = load_as<Ta>(store_as<Tr>(Rz[f]));
+          const Tqt ts = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f]), rr));
+          rk.qt[f * g.N + id] = ts;
+          Ta qin;
+          if constexpr (std::is_same<Tq, Tc>::value && std::is_same<Ta, Tc>::value)
+            qin = ck[f];
+          else
+            qin = load_as<Ta>(K.q[f * g.N + id]);
+          rk.q_out[f * g.N + id] = store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts)));
+        }
+      }
     }
   }
+#if TGV_EARLY_EMIT
+  __syncthreads();
+#endif
 }
 
-template <class Tq, class Tr, class Tc>
-__global__ void __launch_bounds__(NT) residual_tiled(Kernel<Tq, Tr, Tc> K, int tiles_x, int tiles_y, int chunks_z,
-                                                     int remap) {
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
+__global__ void __launch_bounds__(NT, TGV_MIN_WAVES) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
+                                                     int tiles_y, int chunks_z, int remap) {
   __shared__ Tc lds[NF * NPL];
+  __shared__ Tc lds_ri[RI_SLOTS * 5 * NT];
   const Grid& g = K.g;
   // XCD-aware order: hardware block b runs on XCD b % 8; give each XCD a
   // contiguous range of logical tiles so that y-neighbours share an L2.
@@ -338,32 +426,51 @@ __global__ void __launch_bounds__(NT) residual_tiled(Kernel<Tq, Tr, Tc> K, int t
   }
   Ctx<Tc> cx;
   const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
-  for (int p = p_first; p <= p_last; p += 5) {
-    zstep<Tq, Tr, Tc, 0>(K, cx, lds, nxt, off, p, z0, z1, col_valid, col_off, p_last);
+  // plane p = p_first + t sits in RI slot t % 3; the plane emitted with it,
+  // p - 2, in slot (t - 2) % 3 = (t + 1) % 3.
+  for (int p = p_first, t = 0; p <= p_last; p += 5, t += 5) {
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 0>(K, rk, cx, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
     if (p + 1 > p_last) break;
-    zstep<Tq, Tr, Tc, 1>(K, cx, lds, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 1>(K, rk, cx, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
     if (p + 2 > p_last) break;
-    zstep<Tq, Tr, Tc, 2>(K, cx, lds, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 2>(K, rk, cx, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
     if (p + 3 > p_last) break;
-    zstep<Tq, Tr, Tc, 3>(K, cx, lds, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 3>(K, rk, cx, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
     if (p + 4 > p_last) break;
-    zstep<Tq, Tr, Tc, 4>(K, cx, lds, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 4>(K, rk, cx, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
   }
 }
 
 }  // namespace
 
-template <class Tq, class Tr, class Tc>
-hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, const void* q, void* r, hipStream_t st) {
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
+hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
+                        hipStream_t st) {
   const int tiles_x = (g.nx + TX - 1) / TX;
   const int tiles_y = (g.ny + TY - 1) / TY;
   const int chunks_z = (g.nz + KZ - 1) / KZ;
   const long long nb = (long long)tiles_x * tiles_y * chunks_z;
   const int remap = (nb % 8 == 0) ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
-  hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc>), dim3((unsigned)nb), dim3(NT), 0, st, K, tiles_x, tiles_y,
-                     chunks_z, remap);
+  hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED>), dim3((unsigned)nb), dim3(NT), 0, st, K, rk,
+                     tiles_x, tiles_y, chunks_z, remap);
   return hipGetLastError();
+}
+
+template <class Tq, class Tr, class Tc>
+hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, const void* q, void* r, hipStream_t st) {
+  const RkArgs<Tq, Tq, Tc> none{nullptr, nullptr, Tc(0), Tc(0), Tc(0), 1};
+  return launch_tiled<Tq, Tr, Tc, Tq, Tc, false>(g, c, q, r, none, st);
+}
+
+template <class Tq, class Tqt, class Tr, class Tc, class Ta>
+hipError_t launch_residual_rk(const Grid& g, const Coef<Tc>& c, int stage, double dt, const void* q_in, void* q_out,
+                              void* qt, hipStream_t st) {
+  static const double kA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  const RkArgs<Tq, Tqt, Ta> rk{static_cast<Tq*>(q_out), static_cast<Tqt*>(qt), (Ta)kA[stage], (Ta)kB[stage],
+                               (Ta)dt, stage == 0 ? 1 : 0};
+  return launch_tiled<Tq, Tr, Tc, Tqt, Ta, true>(g, c, q_in, nullptr, rk, st);
 }
 
 #define TGV_INST_RES(Tq, Tr, Tc) \
@@ -376,5 +483,17 @@ TGV_INST_RES(float, float, float)
 TGV_INST_RES(float, f16, float)
 TGV_INST_RES(float, bf16, float)
 TGV_INST_RES(f16, f16, float)
+
+#define TGV_INST_RRK(Tq, Tqt, Tr, Tc, Ta)                                                                     \
+  template hipError_t launch_residual_rk<Tq, Tqt, Tr, Tc, Ta>(const Grid&, const Coef<Tc>&, int, double,     \
+                                                              const void*, void*, void*, hipStream_t);
+TGV_INST_RRK(double, double, double, double, double)
+TGV_INST_RRK(double, double, float, float, double)
+TGV_INST_RRK(double, double, float, double, double)
+TGV_INST_RRK(float, float, float, double, double)
+TGV_INST_RRK(float, float, float, float, float)
+TGV_INST_RRK(float, float, f16, float, float)
+TGV_INST_RRK(float, float, bf16, float, float)
+TGV_INST_RRK(f16, f16, f16, float, float)
 
 }  // namespace tgv

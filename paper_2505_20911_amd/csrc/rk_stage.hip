@@ -30,22 +30,20 @@ __global__ void __launch_bounds__(256) rk_stage_kernel(long long n5, Ta A, Ta B,
 #pragma unroll
     for (int e = 0; e < kElems; ++e) {
       const Ta rr = load_as<Ta>(rv.v[e]);
-      const Ta tn = kFirst ? dt * rr : A * load_as<Ta>(tv.v[e]) + dt * rr;
-      const Tqt ts = store_as<Tqt>(tn);
+      const Tqt ts = store_as<Tqt>(rk_register<Ta>(kFirst, A, dt, kFirst ? Ta(0) : load_as<Ta>(tv.v[e]), rr));
       tv.v[e] = ts;
       // Q is advanced with the stored (rounded) register value, as a
       // separate Q~ array would be read back.
-      qv.v[e] = store_as<Tq>(load_as<Ta>(qv.v[e]) + B * load_as<Ta>(ts));
+      qv.v[e] = store_as<Tq>(rk_state<Ta>(B, load_as<Ta>(qv.v[e]), load_as<Ta>(ts)));
     }
     reinterpret_cast<Chunk<Tqt>*>(qt)[t] = tv;
     reinterpret_cast<Chunk<Tq>*>(q)[t] = qv;
   } else if (base < n5) {
     for (long long e = base; e < n5; ++e) {
       const Ta rr = load_as<Ta>(r[e]);
-      const Ta tn = kFirst ? dt * rr : A * load_as<Ta>(qt[e]) + dt * rr;
-      const Tqt ts = store_as<Tqt>(tn);
+      const Tqt ts = store_as<Tqt>(rk_register<Ta>(kFirst, A, dt, kFirst ? Ta(0) : load_as<Ta>(qt[e]), rr));
       qt[e] = ts;
-      q[e] = store_as<Tq>(load_as<Ta>(q[e]) + B * load_as<Ta>(ts));
+      q[e] = store_as<Tq>(rk_state<Ta>(B, load_as<Ta>(q[e]), load_as<Ta>(ts)));
     }
   }
 }

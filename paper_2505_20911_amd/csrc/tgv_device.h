@@ -105,6 +105,21 @@ __device__ __forceinline__ T store_as(Tc x) {
   return Conv<T>::from(x);
 }
 
+// Two-register RK update of one element (Sec. 3.1 update equations), shared
+// by the stand-alone stage kernel and the fused residual + stage kernel so
+// both round identically:  t = A qt + dt r (t = dt r at stage 0), stored as
+// Tqt;  q_new = q + B t_stored.  Explicit fma fixes the contraction.
+__device__ __forceinline__ double fused_ma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fused_ma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <class Ta>
+__device__ __forceinline__ Ta rk_register(bool first, Ta A, Ta dt, Ta qt, Ta r) {
+  return first ? dt * r : fused_ma(A, qt, dt * r);
+}
+template <class Ta>
+__device__ __forceinline__ Ta rk_state(Ta B, Ta q, Ta t) {
+  return fused_ma(B, t, q);
+}
+
 // Grid description passed to kernels by value.
 struct Grid {
   int nx, ny, nz;

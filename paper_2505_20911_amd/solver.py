@@ -1,7 +1,12 @@
 """Time-stepping driver over the C-ABI: owns Q, Q~, R and the integrals
 workspace on one GPU and enqueues the step (paper Sec. 3.1: per RK stage one
 residual evaluation then the two-register update) on one stream.  History
-samples of the integrals stay on the device until read."""
+samples of the integrals stay on the device until read.
+
+fused=True (default) uses ns_residual_rk_stage: each stage is one pass that
+reads Q from one buffer and writes the advanced Q to the other (the stencil
+must see the old Q around every point), so Q ping-pongs between two buffers
+and R is never stored.  fused=False calls ns_residual then rk_stage."""
 from __future__ import annotations
 
 import torch
@@ -11,24 +16,40 @@ from .tgv import Params, Prec
 
 
 class TGVSolver:
-    def __init__(self, params: Params, prec: Prec, device="cuda", stream=None):
+    def __init__(self, params: Params, prec: Prec, device="cuda", stream=None, fused: bool = True):
         self.params = params
         self.prec = prec
         self.device = torch.device(device)
         self.stream = stream
+        self.fused = fused
         shape = params.shape
-        self.q = torch.empty(shape, dtype=prec.q, device=self.device)
+        self._q = [torch.empty(shape, dtype=prec.q, device=self.device)]
+        if fused:
+            self._q.append(torch.empty(shape, dtype=prec.q, device=self.device))
+            self.r = None
+        else:
+            self.r = torch.empty(shape, dtype=prec.r, device=self.device)
+        self._cur = 0
         self.qt = torch.zeros(shape, dtype=prec.qt, device=self.device)
-        self.r = torch.empty(shape, dtype=prec.r, device=self.device)
         nbytes = tgv.flow_integrals_workspace_bytes(params)
         self.work = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=self.device)
+
+    @property
+    def q(self) -> torch.Tensor:
+        """The current state Q."""
+        return self._q[self._cur]
 
     def init(self) -> None:
         tgv.tgv_init(self.params, self.q, self.stream)
 
     def stage(self, i: int, dt: float) -> None:
-        tgv.ns_residual(self.params, self.prec, self.q, self.r, self.stream)
-        tgv.rk_stage(self.params, self.prec, i, dt, self.q, self.qt, self.r, self.stream)
+        if self.fused:
+            tgv.ns_residual_rk_stage(self.params, self.prec, i, dt, self._q[self._cur], self._q[1 - self._cur],
+                                     self.qt, self.stream)
+            self._cur = 1 - self._cur
+        else:
+            tgv.ns_residual(self.params, self.prec, self.q, self.r, self.stream)
+            tgv.rk_stage(self.params, self.prec, i, dt, self.q, self.qt, self.r, self.stream)
 
     def step(self, dt: float) -> None:
         for i in range(3):

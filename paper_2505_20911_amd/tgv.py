@@ -44,6 +44,8 @@ _EXPORTS = {
                      ctypes.c_void_p], ctypes.c_int),
     "rk_stage": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_int, ctypes.c_double,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ns_residual_rk_stage": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_int, ctypes.c_double,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "flow_integrals_workspace_bytes": ([ctypes.POINTER(NsParams)], ctypes.c_size_t),
     "flow_integrals": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -181,6 +183,14 @@ def rk_stage(params: Params, prec: Prec, stage: int, dt: float, q: torch.Tensor,
     _check("rk_stage", load().rk_stage(ctypes.byref(params.c()), ctypes.byref(prec.c()), int(stage), float(dt),
                                        _ptr(q, "q", prec.q, n5), _ptr(qt, "qt", prec.qt, n5),
                                        _ptr(r, "r", prec.r, n5), _stream(stream)))
+
+
+def ns_residual_rk_stage(params: Params, prec: Prec, stage: int, dt: float, q_in: torch.Tensor,
+                         q_out: torch.Tensor, qt: torch.Tensor, stream=None) -> None:
+    n5 = 5 * params.N
+    _check("ns_residual_rk_stage", load().ns_residual_rk_stage(
+        ctypes.byref(params.c()), ctypes.byref(prec.c()), int(stage), float(dt), _ptr(q_in, "q_in", prec.q, n5),
+        _ptr(q_out, "q_out", prec.q, n5), _ptr(qt, "qt", prec.qt, n5), _stream(stream)))
 
 
 def flow_integrals_workspace_bytes(params: Params) -> int:

@@ -49,8 +49,11 @@ def test_init_matches_oracle(n, dtype):
         # correctly rounded FP64 values; sin/cos of two libraries may differ by
         # an FP64 ulp, which can move a value across a rounding boundary: allow
         # one unit of the storage precision.
+        # Values near zero (sin of a multiple of pi) differ between the two
+        # libraries in absolute terms: floor of 4 FP64 ulps of the field scale.
         u = UNIT_ROUNDOFF[dtype]
-        assert np.all(np.abs(got - ref) <= 2 * u * np.abs(ref) + 1e-300)
+        floor = 4e-16 * np.abs(ref).reshape(5, -1).max(1)[:, None, None, None]
+        assert np.all(np.abs(got - ref) <= 2 * u * np.abs(ref) + floor + 1e-300)
         exact = widened(rounded(ref, dtype)) if dtype != torch.bfloat16 else None
         if exact is not None:
             assert np.mean(got == exact) > 0.999
@@ -110,7 +113,12 @@ def test_residual_uniform_state_is_exactly_zero():
     q[4] = p0 / 0.4 + 0.5 * rho * sum(x * x for x in U)
     r = torch.full_like(q, 7.0)
     tgv.ns_residual(p, tgv.PRESETS["DP"], q, r)
-    assert torch.all(r == 0)
+    nz = (r != 0)
+    if nz.any():
+        idx = nz.nonzero()[:8].tolist()
+        say("  nonzero:", int(nz.sum()), "max", float(r.abs().max()), "at", idx,
+            "values", [float(r[tuple(i)]) for i in idx])
+    assert not nz.any()
 
 
 def test_residual_is_deterministic():
@@ -141,15 +149,60 @@ def test_rk_stage_matches_oracle(form, stage):
         qt_in = qt.clone()
     qd, qtd = q.to(DEV), qt_in.to(DEV)
     tgv.rk_stage(p, prec, stage, dt, qd, qtd, r.to(DEV))
-    O.rk_stage(stage, dt, q64, qt64, r64)
+    A, B = O.RK_A[stage], O.RK_B[stage]
+    At = np.abs(A * qt64)  # |A qt| with the register before the stage
+    q_in = q64.copy()
+    O.rk_stage(stage, dt, q64, qt64, r64)  # updates q64, qt64 in place
     ua = 2.0 ** -53 if torch.float64 in (prec.q, prec.compute) else 2.0 ** -24
     uq, ut = UNIT_ROUNDOFF[prec.q], UNIT_ROUNDOFF[prec.qt]
+    # half the smallest subnormal spacing of the storage types (FP16 register
+    # values near zero round on an absolute grid)
+    tiny_t = {torch.float16: 2.0 ** -25, torch.bfloat16: 2.0 ** -134}.get(prec.qt, 0.0)
+    tiny_q = {torch.float16: 2.0 ** -25, torch.bfloat16: 2.0 ** -134}.get(prec.q, 0.0)
     got_t, got_q = widened(qtd), widened(qd)
     assert np.all(np.isfinite(got_t)) and np.all(np.isfinite(got_q))
-    tol_t = 4 * ua * (np.abs(qt64) + dt * np.abs(r64)) + ut * np.abs(qt64)
-    assert np.all(np.abs(got_t - qt64) <= tol_t + 1e-300)
-    tol_q = 4 * ua * np.abs(q64) + uq * np.abs(q64) + 2 * np.abs(got_t - qt64) + 1e-300
-    assert np.all(np.abs(got_q - q64) <= tol_q)
+    # register: two roundings in the arithmetic type on the operand scale, one
+    # rounding to its storage type
+    tol_t = 2 * ua * (At + dt * np.abs(r64)) + ut * np.abs(qt64) + tiny_t
+    dt_err = np.abs(got_t - qt64)
+    assert np.all(dt_err <= tol_t + 1e-300)
+    # state: one fma on the scale |q| + |B t|, one rounding to storage, plus
+    # the register difference carried through B
+    tol_q = 2 * ua * (np.abs(q_in) + abs(B) * np.abs(qt64)) + uq * np.abs(q64) + abs(B) * dt_err + tiny_q
+    assert np.all(np.abs(got_q - q64) <= tol_q + 1e-300)
+
+
+# ---------------------------------------------------------------- fused residual + RK stage
+@pytest.mark.parametrize("form", ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"])
+@pytest.mark.parametrize("n", [(24, 32, 40), (5, 6, 7), (64, 8, 70)])
+def test_fused_stage_equals_residual_then_stage(form, n):
+    """ns_residual_rk_stage is the same computation as ns_residual followed by
+    rk_stage (R rounded to its storage type in both): bitwise equal."""
+    say("fused", form, n)
+    prec = tgv.PRESETS[form]
+    p = tgv.Params(n=n)
+    q0 = rounded(S.random_state(n, 2, smooth=True), prec.q).to(DEV)
+    qt0 = rounded(np.random.default_rng(1).standard_normal(p.shape) * 1e-3, prec.qt).to(DEV)
+    dt = 1e-3
+    for stage in (0, 1, 2):
+        qa, qta, r = q0.clone(), qt0.clone(), torch.empty(p.shape, dtype=prec.r, device=DEV)
+        tgv.ns_residual(p, prec, qa, r)
+        tgv.rk_stage(p, prec, stage, dt, qa, qta, r)
+        qb, qtb = torch.empty_like(q0), qt0.clone()
+        tgv.ns_residual_rk_stage(p, prec, stage, dt, q0, qb, qtb)
+        assert torch.equal(qtb, qta), (stage, (qtb.double() - qta.double()).abs().max())
+        assert torch.equal(qb, qa), (stage, (qb.double() - qa.double()).abs().max())
+
+
+def test_fused_solver_trajectory_equals_split_solver():
+    p = tgv.Params(n=(32, 32, 32))
+    a = TGVSolver(p, tgv.PRESETS["DP"], fused=True)
+    b = TGVSolver(p, tgv.PRESETS["DP"], fused=False)
+    a.init()
+    b.init()
+    ha = a.run(7, 3.7e-3, every=1)
+    hb = b.run(7, 3.7e-3, every=1)
+    assert torch.equal(a.q, b.q) and torch.equal(ha, hb)
 
 
 # ---------------------------------------------------------------- integrals
