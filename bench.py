@@ -35,7 +35,21 @@ def parse():
     ap.add_argument("--paths", default="fused,split", help="fused and/or split residual + stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the oracle sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 launches), to calibrate the "
+                         "FETCH_SIZE / WRITE_SIZE counters against known bytes")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
 def nbytes(dtype):
@@ -150,6 +164,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
     import torch
     from paper_2505_20911_amd import tgv
     tgv.load()

@@ -114,7 +114,15 @@ tgv::Coef<Tc> make_coef(const ns_params_t* p) {
   c.gm1 = (Tc)(p->gamma - 1.0);
   c.gm2 = (Tc)(p->gamma * p->mach * p->mach);
   c.ire = (Tc)(1.0 / p->reynolds);
-  c.kap = (Tc)(1.0 / ((p->gamma - 1.0) * p->mach * p->mach * p->prandtl * p->reynolds));
+  const double kap = 1.0 / ((p->gamma - 1.0) * p->mach * p->mach * p->prandtl * p->reynolds);
+  c.kap = (Tc)kap;
+  for (int d = 0; d < 3; ++d) {
+    const double h = p->L[d] / p->n[d];
+    const double c2 = 1.0 / (12.0 * h * h);
+    c.vis2[d] = (Tc)(c2 / p->reynolds);
+    c.vis2l[d] = (Tc)(c2 * (4.0 / 3.0) / p->reynolds);
+    c.kap2[d] = (Tc)(c2 * kap);
+  }
   c.viscous = p->viscous;
   return c;
 }

@@ -41,16 +41,13 @@ namespace tgv {
 
 namespace {
 
-#ifndef TGV_TILE_Y
-#define TGV_TILE_Y 4
-#endif
-#ifndef TGV_MIN_WAVES
-#define TGV_MIN_WAVES 1
-#endif
-#ifndef TGV_EARLY_EMIT
-#define TGV_EARLY_EMIT 0
-#endif
-constexpr int TX = 64, TY = TGV_TILE_Y, NT = TX * TY;
+constexpr int TX = 64, TY = 4, NT = TX * TY;
+// Waves per SIMD the register allocation must allow: FP64 arithmetic is
+// latency-bound at one wave per SIMD and gains from a second one even at the
+// price of a few spilled registers; the FP32 forms are VALU-bound and fit two
+// waves anyway (measured at 512^3).
+template <class Tc>
+constexpr int kWavesPerEU = sizeof(Tc) == 8 ? 2 : 1;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
 constexpr int NF = 10;
@@ -84,7 +81,7 @@ __device__ __forceinline__ Tc S2(Tc m2, Tc m1, Tc c, Tc p1, Tc p2) {
 
 template <class Tc>
 __device__ __forceinline__ void primitives(const Tc q[5], Tc* out, const Coef<Tc>& c) {
-  const Tc ir = Tc(1) / q[0];
+  const Tc ir = recip(q[0]);
 #pragma unroll
   for (int f = 0; f < 5; ++f) out[f] = q[f];
   const Tc u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
@@ -132,8 +129,9 @@ struct WinNb {
 // adds into R and writes the three gradients D_d u_a.  Neighbour values are
 // consumed one field at a time to keep few of them live.
 template <class Tc, int d, class Nb>
-__device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, const Coef<Tc>& c, Tc sc1, Tc sc2,
-                                                Tc (&R)[5], Tc (&G)[3]) {
+__device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, const Coef<Tc>& c, Tc (&R)[5],
+                                                Tc (&G)[3]) {
+  const Tc sc1 = c.c1[d];
   const Tc h = Tc(0.5);
   Tc ud[4], pn[4];
 #pragma unroll
@@ -179,12 +177,11 @@ __device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, cons
 #pragma unroll
       for (int s = 0; s < 4; ++s) un[s] = (a == d) ? ud[s] : nb(F_U + a, s);
       G[a] = sc1 * ((a == d) ? Sud : S1(un[0], un[1], un[2], un[3]));
-      const Tc l = sc2 * S2(un[0], un[1], c0[F_U + a], un[2], un[3]);
-      const Tc v = (a == d) ? c.ire * Tc(4.0 / 3.0) * l : c.ire * l;
+      const Tc v = ((a == d) ? c.vis2l[d] : c.vis2[d]) * S2(un[0], un[1], c0[F_U + a], un[2], un[3]);
       R[1 + a] += v;
       R[4] += c0[F_U + a] * v;
     }
-    R[4] += c.kap * sc2 * S2(nb(F_T, 0), nb(F_T, 1), c0[F_T], nb(F_T, 2), nb(F_T, 3));
+    R[4] += c.kap2[d] * S2(nb(F_T, 0), nb(F_T, 1), c0[F_T], nb(F_T, 2), nb(F_T, 3));
   }
 }
 
@@ -258,12 +255,12 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   for (int k = 0; k < NF; ++k) c0[k] = lds[k * NPL + own];
 #pragma unroll
   for (int k = 0; k < 5; ++k) cx.W[PH][k] = c0[k];
-  cx.W[PH][W_IR] = Tc(1) / c0[F_RHO];
+  cx.W[PH][W_IR] = recip(c0[F_RHO]);
   Tc R[5] = {0, 0, 0, 0, 0};
   {
     Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
-    direction_terms<Tc, 0>(LdsNb<Tc, 1>{lds, own}, c0, c, c.c1[0], c.c2[0], R, Gx);
-    direction_terms<Tc, 1>(LdsNb<Tc, HX>{lds, own}, c0, c, c.c1[1], c.c2[1], R, Gy);
+    direction_terms<Tc, 0>(LdsNb<Tc, 1>{lds, own}, c0, c, R, Gx);
+    direction_terms<Tc, 1>(LdsNb<Tc, HX>{lds, own}, c0, c, R, Gy);
     cx.A[PH][0] = Gx[2];
     cx.A[PH][1] = Gy[2];
     cx.A[PH][2] = Gx[0] + Gy[1];
@@ -304,9 +301,6 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
 #pragma unroll
     for (int f = 0; f < 5; ++f) ri[f * NT] = R[f];
   }
-#if !TGV_EARLY_EMIT
-  __syncthreads();
-#endif
 
   // 3. emit plane k = p - 2 (window slots: k-2 .. k+2)
   if (emit) {
@@ -321,7 +315,7 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
     Tc ck[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) ck[f] = derived(cx.W[K0], f, c);
-    direction_terms<Tc, 2>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W, c}, ck, c, c.c1[2], c.c2[2], Rz, Gz);
+    direction_terms<Tc, 2>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W, c}, ck, c, Rz, Gz);
     if (c.viscous) {
       const Tc* u0 = ck + F_U;
       // z-mixed: X_x += D_z(w_x), X_y += D_z(w_y), X_z += D_z(u_x + v_y)
@@ -365,13 +359,12 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
       }
     }
   }
-#if TGV_EARLY_EMIT
+  // the next plane overwrites the LDS plane
   __syncthreads();
-#endif
 }
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
-__global__ void __launch_bounds__(NT, TGV_MIN_WAVES) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
+__global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
                                                      int tiles_y, int chunks_z, int remap) {
   __shared__ Tc lds[NF * NPL];
   __shared__ Tc lds_ri[RI_SLOTS * 5 * NT];

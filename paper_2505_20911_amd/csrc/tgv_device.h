@@ -61,12 +61,21 @@ struct Conv<float> {
   __device__ __forceinline__ static float from(float x) { return x; }
 };
 
+// An FP32 value is first rounded in FP32 and then to FP16 (the arithmetic
+// type, then the storage type).  The empty asm pins the FP32 value so the
+// compiler cannot merge a producing fma with the conversion into a mixed
+// fma that rounds only once.
+__device__ __forceinline__ f16 f32_to_f16(float x) {
+  asm volatile("" : "+v"(x));
+  return (f16)x;
+}
+
 template <>
 struct Conv<f16> {
   __device__ __forceinline__ static double load_f64(f16 v) { return (double)(float)v; }
   __device__ __forceinline__ static float load_f32(f16 v) { return (float)v; }
-  __device__ __forceinline__ static f16 from(double x) { return (f16)f64_to_f32_odd(x); }
-  __device__ __forceinline__ static f16 from(float x) { return (f16)x; }
+  __device__ __forceinline__ static f16 from(double x) { return f32_to_f16(f64_to_f32_odd(x)); }
+  __device__ __forceinline__ static f16 from(float x) { return f32_to_f16(x); }
 };
 
 template <>
@@ -120,6 +129,21 @@ __device__ __forceinline__ Ta rk_state(Ta B, Ta q, Ta t) {
   return fused_ma(B, t, q);
 }
 
+// 1/x from the hardware reciprocal estimate refined by Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error: two steps
+// in FP64, one in FP32, leave it at the rounding level of the type (within
+// an ulp or two; x is a density, far from the overflow/underflow range).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
 // Grid description passed to kernels by value.
 struct Grid {
   int nx, ny, nz;
@@ -137,6 +161,9 @@ struct Coef {
   Tc gm2;     // gamma M^2
   Tc ire;     // 1 / Re
   Tc kap;     // 1 / ((gamma - 1) M^2 Pr Re)
+  Tc vis2[3];   // (1/Re) / (12 h_d^2): transverse viscous second derivative
+  Tc vis2l[3];  // (4/3)(1/Re) / (12 h_d^2): longitudinal (D2_a u_a counted in X_a too)
+  Tc kap2[3];   // kappa / (12 h_d^2): heat flux
   int viscous;
 };
 
