@@ -28,17 +28,45 @@ ALL_FORMS = ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--forms", default=",".join(ALL_FORMS))
     ap.add_argument("--paths", default="fused,split", help="fused and/or split residual + stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=128, help="grid of the oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=256, help="grid of the oracle sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 launches), to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = ["paper_2505_20911_amd/csrc/residual_tiled.hip", "paper_2505_20911_amd/csrc/tgv_device.h"]
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM-side bytes per launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none for this kernel or the
+    kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    k = d.get("kernels", {}).get(key)
+    return None if k is None else k.get("traffic_bytes_per_launch")
 
 
 def copy_calibration(mib):
@@ -208,7 +236,9 @@ def main():
                    "grid": [n, n, n], "form": head_key, "path": head["path"]},
         "roofline": {"bound": "hbm", "kernel": "ns_residual_rk_stage" if kname == "fused" else "ns_residual",
                      "achieved": hk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hk["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": hk["gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(("ns_residual_rk_stage" if kname == "fused" else "ns_residual")
+                                                 + f"/{head_key}/{n}"),
                      "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"]},
         "forms": results,
     }

@@ -41,7 +41,7 @@ namespace tgv {
 
 namespace {
 
-constexpr int TX = 64, TY = 4, NT = TX * TY;
+constexpr int TX = 64, TY = 8, NT = TX * TY;
 // Waves per SIMD the register allocation must allow: FP64 arithmetic is
 // latency-bound at one wave per SIMD and gains from a second one even at the
 // price of a few spilled registers; the FP32 forms are VALU-bound and fit two
@@ -52,7 +52,6 @@ constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
 constexpr int NF = 10;
 enum { F_RHO = 0, F_M = 1, F_E = 4, F_U = 5, F_P = 8, F_T = 9 };
-constexpr int KZ = 64;  // planes per block
 
 // Fields kept per plane in the z-window: the conserved variables and 1/rho;
 // u, v, w, p and T are re-derived from them where the z-stencils need them.
@@ -365,21 +364,24 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
 __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
-                                                     int tiles_y, int chunks_z, int remap) {
+                                                     int tiles_y, int kz, int remap) {
   __shared__ Tc lds[NF * NPL];
   __shared__ Tc lds_ri[RI_SLOTS * 5 * NT];
   const Grid& g = K.g;
   // XCD-aware order: hardware block b runs on XCD b % 8; give each XCD a
-  // contiguous range of logical tiles so that y-neighbours share an L2.
-  const int nb = tiles_x * tiles_y * chunks_z;
+  // contiguous range of logical tiles, x fastest, so that the blocks resident
+  // on one XCD at a time cover whole rows of tiles and their x- and y-halo
+  // loads meet in that XCD's L2 (at 512^3: 32 resident tiles = 512 x 32
+  // columns, halo fetch 1.16x the tile's own bytes instead of 1.6x).
+  const int nb = gridDim.x;
   int b = blockIdx.x;
   if (remap) b = (b % 8) * (nb / 8) + b / 8;
-  const int ty_t = b % tiles_y;
-  const int tx_t = (b / tiles_y) % tiles_x;
+  const int tx_t = b % tiles_x;
+  const int ty_t = (b / tiles_x) % tiles_y;
   const int cz = b / (tiles_y * tiles_x);
   const int x0 = tx_t * TX, y0 = ty_t * TY;
-  const int z0 = cz * KZ;
-  const int z1 = min(z0 + KZ, g.nz);
+  const int z0 = cz * kz;
+  const int z1 = min(z0 + kz, g.nz);
 
   const int tid = threadIdx.x;
   // wrapped (x, y) offsets of the plane points this thread loads (fixed over z)
@@ -441,12 +443,16 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
                         hipStream_t st) {
   const int tiles_x = (g.nx + TX - 1) / TX;
   const int tiles_y = (g.ny + TY - 1) / TY;
-  const int chunks_z = (g.nz + KZ - 1) / KZ;
-  const long long nb = (long long)tiles_x * tiles_y * chunks_z;
-  const int remap = (nb % 8 == 0) ? 1 : 0;
+  // Planes per block: long z-marches amortise the 4 halo planes a block
+  // loads at its ends, but the grid must still hold enough blocks to fill
+  // the chip several times over.
+  int kz = 128;
+  while (kz > 16 && (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz) < 2048) kz /= 2;
+  const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
+  const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
   hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED>), dim3((unsigned)nb), dim3(NT), 0, st, K, rk,
-                     tiles_x, tiles_y, chunks_z, remap);
+                     tiles_x, tiles_y, kz, remap);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ from tgv_testutil import UNIT_ROUNDOFF, oracle_params, rounded, term_scale, wide
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
-GRIDS = [(16, 16, 16), (32, 32, 32), (24, 32, 40), (5, 6, 7)]
+GRIDS = [(16, 16, 16), (32, 32, 32), (24, 32, 40), (5, 6, 7), (70, 20, 37), (128, 16, 64)]
 
 
 def say(*a):
@@ -282,3 +282,43 @@ def test_residual_full_size_sampled(n):
     scale = term_scale(p.n, p.L, p.gamma, O.init(oracle_params(tgv.Params(n=(16, 16, 16)))))
     scale = scale * (16 / n) ** -1  # same field magnitudes, h smaller by 16/n
     assert np.all(np.abs(got - ref) <= 1e-12 * scale[None, :])
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_fused_stage_full_size_sampled(n):
+    """The benchmark's launch: one fused residual + RK stage (stage 2 of 3,
+    so both registers are read) in FP64 on the full grid, compared at 2000
+    sampled points (plus corners and edges) with the oracle's pointwise
+    residual combined by the stage formula in FP64."""
+    say("fused full size sampled", n)
+    p = tgv.Params(n=(n, n, n))
+    po = oracle_params(p)
+    q64 = O.init(po)
+    q64[1:4] *= 1.0 + 0.01 * np.cos(np.arange(n))[None, None, None, :]
+    rng = np.random.default_rng(n + 1)
+    idx = rng.choice(p.N, 2000, replace=False)
+    edge = [0, n - 1, n * n - 1, n * n * (n - 1), p.N - 1, n // 2 + n * n * (n // 2), n * n * (n - 2) + 3]
+    idx = np.unique(np.concatenate([idx, edge])).astype(np.int64)
+    R = O.residual_at(po, q64, idx)                   # (points, 5)
+    q_s = q64.reshape(5, -1)[:, idx].T.copy()
+    qt_s = 0.5 * q_s                                  # the Q~ register below is Q / 2, exact
+    q = torch.from_numpy(q64).to(DEV)
+    del q64
+    qt = q * 0.5
+    q_out = torch.empty_like(q)
+    stage, dt = 1, 2.3125e-4
+    tgv.ns_residual_rk_stage(p, tgv.PRESETS["DP"], stage, dt, q, q_out, qt)
+    ti = torch.from_numpy(idx).to(DEV)
+    got_qt = qt.reshape(5, -1)[:, ti].T.cpu().numpy()
+    got_q = q_out.reshape(5, -1)[:, ti].T.cpu().numpy()
+    del q, qt, q_out
+    torch.cuda.empty_cache()
+    A, B = O.RK_A[stage], O.RK_B[stage]
+    ref_qt = A * qt_s + dt * R
+    ref_q = q_s + B * ref_qt
+    scale = term_scale(p.n, p.L, p.gamma, O.init(oracle_params(tgv.Params(n=(16, 16, 16))))) * (n / 16)
+    u = UNIT_ROUNDOFF[torch.float64]
+    tol_qt = 4 * u * (np.abs(A * qt_s) + dt * np.abs(R)) + dt * 1e-12 * scale[None, :]
+    tol_q = 4 * u * (np.abs(q_s) + np.abs(B * ref_qt)) + B * tol_qt
+    assert np.all(np.abs(got_qt - ref_qt) <= tol_qt), np.max(np.abs(got_qt - ref_qt) / tol_qt)
+    assert np.all(np.abs(got_q - ref_q) <= tol_q), np.max(np.abs(got_q - ref_q) / tol_q)
