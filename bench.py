@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--forms", default=",".join(ALL_FORMS))
     ap.add_argument("--paths", default="fused,split", help="fused and/or split residual + stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint kernels and gradient timing")
     ap.add_argument("--cpu-n", type=int, default=256, help="grid of the oracle sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 launches), to calibrate the "
@@ -95,6 +96,7 @@ def time_form(form, n, steps, warmup, dt, fused):
 
     prec = tgv.PRESETS[form]
     p = tgv.Params(n=(n, n, n))
+    torch.cuda.reset_peak_memory_stats()
     s = TGVSolver(p, prec, fused=fused)
     s.init()
     every = 10
@@ -161,10 +163,75 @@ def time_form(form, n, steps, warmup, dt, fused):
         "gpu_ms_per_step": gpu_ms / steps,
         "kernels": kernels,
         "finite": finite,
+        "peak_device_gb": torch.cuda.max_memory_allocated() / 1e9,  # Q, Q~, R or Q_out, workspace
         "K_first": float(hist[0, 0]),
     }
     del s, hist
     torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_leg(n, form="DP", launches=5):
+    """Average duration and algorithmic bandwidth of the three adjoint entry
+    points on an n^3 grid (one warm-up launch each, then `launches` timed with
+    HIP events on the launch stream), and the wall time of the 128^3 gradient
+    workload: 400 steps, 20 snapshot buffers, forward + reverse sweep."""
+    import torch
+    from paper_2505_20911_amd import tgv
+    from paper_2505_20911_amd.adjoint import CheckpointedDissipation
+    prec = tgv.PRESETS[form]
+    p = tgv.Params(n=(n, n, n))
+    N, b = p.N, nbytes(prec.q)
+    q = torch.empty(p.shape, dtype=prec.q, device="cuda")
+    tgv.tgv_init(p, q)
+    rbar = torch.full(p.shape, 1e-3, dtype=prec.q, device="cuda")
+    qbar = torch.zeros(p.shape, dtype=prec.q, device="cuda")
+    zeta = torch.zeros(p.shape, dtype=prec.q, device="cuda")
+    aw = torch.empty(tgv.ns_residual_adjoint_workspace_bytes(p, prec) // 8 + 1, dtype=torch.float64, device="cuda")
+    ew = torch.empty(tgv.flow_integrals_adjoint_workspace_bytes(p, prec) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    calls = {
+        "ns_residual_adjoint": (lambda: tgv.ns_residual_adjoint(p, prec, q, rbar, qbar, aw), 5 * N * 4 * b),
+        "rk_stage_adjoint": (lambda: tgv.rk_stage_adjoint(p, prec, 1, 1e-4, qbar, zeta, rbar), 5 * N * 4 * b),
+        "flow_integrals_adjoint": (lambda: tgv.flow_integrals_adjoint(p, prec, q, 1e-3, qbar, ew), 4 * N * 3 * b),
+    }
+    stream = torch.cuda.current_stream()
+    out = {"grid": [n, n, n], "form": form, "kernels": {}}
+    for name, (fn, algo) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(launches):
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            e.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(e))
+        avg = sum(ms) / len(ms)
+        out["kernels"][name] = {"avg_ms": avg, "bytes_per_launch": algo, "gbs": algo / (avg * 1e-3) / 1e9,
+                                "frac_hbm": algo / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del q, rbar, qbar, zeta, aw, ew
+    torch.cuda.empty_cache()
+    # the gradient workload of the differentiation form
+    grad = {}
+    for gform in ("DP", "SP"):
+        gp = tgv.Params(n=(128, 128, 128))
+        gprec = tgv.PRESETS[gform]
+        q0 = torch.empty(gp.shape, dtype=gprec.q, device="cuda")
+        tgv.tgv_init(gp, q0)
+        runner = CheckpointedDissipation(gp, gprec, 9.25e-4, 400, slots=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = runner.forward(q0)
+        g = runner.backward(q0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        grad[gform] = {"wall_s": wall, "advances": runner.advances, "J": J,
+                       "finite": bool(torch.isfinite(g).all())}
+        del runner, q0, g
+        torch.cuda.empty_cache()
+    out["gradient_128_400steps_20slots"] = grad
     return out
 
 
@@ -242,6 +309,14 @@ def main():
                      "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"]},
         "forms": results,
     }
+    if not args.no_adjoint:
+        print(f"[bench] adjoint kernels at {n}^3 and the 128^3 gradient workload", file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_leg(n)
+        ak = line["adjoint"]["kernels"]
+        print("[bench] adjoint: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['gbs']:.0f} GB/s" for k, v in ak.items())
+              + "; gradient " + ", ".join(f"{k} {v['wall_s']:.2f} s" for k, v in
+                                          line["adjoint"]["gradient_128_400steps_20slots"].items()),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on {args.cpu_n}^3", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_n)

@@ -1,10 +1,18 @@
 // Flow integrals of paper Sec. 4.1 (volume-averaged kinetic energy K and
 // solenoidal dissipation eps^S), plus K_rho and the means of the conserved
 // fields.  Everything -- loads, the 4th-order velocity gradient and the
-// accumulation -- is FP64 whatever the storage type of Q.  Deterministic
-// two-pass reduction: pass 1 gives one row of 8 partial sums per block (fixed
-// point-to-thread mapping, wavefront shuffles then LDS across waves); pass 2
-// sums the rows in a fixed order in a single block.
+// accumulation -- is FP64 whatever the storage type of Q.
+//
+// Pass 1 marches a 64 x 4 tile of (x, y) columns along z, like the residual
+// kernel: each plane of the tile plus a 2-point halo is loaded once (rho and
+// the momenta, coalesced along x), turned into velocities in LDS, and each
+// thread takes the in-plane parts of the vorticity at its own column from
+// LDS and the z-parts from a 5-plane register window of u and v.  Only the
+// components the vorticity needs are differentiated:
+//   w1 = D_y w - D_z v,  w2 = D_z u - D_x w,  w3 = D_x v - D_y u.
+// Deterministic two-pass reduction: pass 1 gives one row of 8 partial sums
+// per block (fixed point-to-thread mapping, wavefront shuffles then LDS
+// across waves); pass 2 sums the rows in a fixed order in a single block.
 #include "tgv_device.h"
 #include "tgv_kernels.h"
 
@@ -12,28 +20,27 @@ namespace tgv {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPointsPerThread = 8;
+constexpr int IX = 64, IY = 4, kThreads = IX * IY;
+constexpr int IHX = IX + 4, IHY = IY + 4, IPL = IHX * IHY;  // plane incl. halo
+constexpr int ILOADS = (IPL + kThreads - 1) / kThreads;
 
-__device__ __forceinline__ long long wrap_shift(const Grid& g, long long id, int i, int j, int k, int d, int s) {
-  if (d == 0) {
-    int t = i + s;
-    t += (t < 0) ? g.nx : 0;
-    t -= (t >= g.nx) ? g.nx : 0;
-    return id + (t - i);
-  } else if (d == 1) {
-    int t = j + s;
-    t += (t < 0) ? g.ny : 0;
-    t -= (t >= g.ny) ? g.ny : 0;
-    return id + (long long)(t - j) * g.nx;
-  }
-  int t = k + s;
-  t += (t < 0) ? g.nz : 0;
-  t -= (t >= g.nz) ? g.nz : 0;
-  return id + (long long)(t - k) * g.plane;
+struct IntLaunch {
+  int tiles_x, tiles_y, kz;
+  long long blocks;
+};
+
+// Planes per block: as long as the grid still fills the chip several times.
+IntLaunch int_launch(const Grid& g) {
+  IntLaunch L;
+  L.tiles_x = (g.nx + IX - 1) / IX;
+  L.tiles_y = (g.ny + IY - 1) / IY;
+  L.kz = 64;
+  while (L.kz > 8 && (long long)L.tiles_x * L.tiles_y * ((g.nz + L.kz - 1) / L.kz) < 4096) L.kz /= 2;
+  L.blocks = (long long)L.tiles_x * L.tiles_y * ((g.nz + L.kz - 1) / L.kz);
+  return L;
 }
 
-// Sum of v over the 256 threads of the block; valid in thread 0.
+// Sum of v over the block; valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* lds) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -46,49 +53,110 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;
 }
 
-template <class Tq>
-__device__ __forceinline__ void vel(const Tq* __restrict__ q, long long N, long long id, double u[3]) {
-  const double ir = 1.0 / load_as<double>(q[id]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) u[a] = load_as<double>(q[(a + 1) * N + id]) * ir;
+// i in [-n, 2n)
+__device__ __forceinline__ int wrap(int i, int n) {
+  i += (i < 0) ? n : 0;
+  i -= (i >= n) ? n : 0;
+  return i;
 }
 
 template <class Tq>
 __global__ void __launch_bounds__(kThreads) integrals_pass1(Grid g, Coef<double> c, const Tq* __restrict__ q,
-                                                            double* __restrict__ work) {
-  __shared__ double lds[4];
+                                                            double* __restrict__ work, int tiles_x, int tiles_y,
+                                                            int kz) {
+  __shared__ double vel[2][3][IPL];  // double-buffered velocity plane
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const int x0 = (b % tiles_x) * IX;
+  const int y0 = ((b / tiles_x) % tiles_y) * IY;
+  const int z0 = (b / (tiles_x * tiles_y)) * kz;
+  const int z1 = min(z0 + kz, g.nz);
+  const int tid = threadIdx.x;
+
+  // plane slots this thread loads: wrapped offset within a plane, and
+  // whether the slot is one of the tile's own (interior, in-grid) points
+  long long off[ILOADS];
+  bool own[ILOADS];
+#pragma unroll
+  for (int l = 0; l < ILOADS; ++l) {
+    const int s = tid + l * kThreads;
+    const int lx = s % IHX, ly = s / IHX;
+    int x = (x0 - 2 + lx) % g.nx, y = (y0 - 2 + ly) % g.ny;  // the halo may wrap more than once
+    x += (x < 0) ? g.nx : 0;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
+    own[l] = s < IPL && lx >= 2 && lx < IX + 2 && ly >= 2 && ly < IY + 2 && x0 - 2 + lx < g.nx &&
+             y0 - 2 + ly < g.ny;
+  }
+  const int tx = tid % IX, ty = tid / IX;
+  const bool col_valid = x0 + tx < g.nx && y0 + ty < g.ny;
+  const int c0 = (ty + 2) * IHX + tx + 2;  // own column in the LDS plane
+
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const long long per_block = (long long)kThreads * kPointsPerThread;
-  const long long start = (long long)blockIdx.x * per_block;
-  for (int e = 0; e < kPointsPerThread; ++e) {
-    const long long id = start + (long long)e * kThreads + threadIdx.x;
-    if (id >= g.N) break;
-    const int i = (int)(id % g.nx), j = (int)((id / g.nx) % g.ny), k = (int)(id / g.plane);
-    double u0[3];
-    vel(q, g.N, id, u0);
-    const double rho = load_as<double>(q[id]);
-    const double uu = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
-    double G[3][3];  // G[a][d] = D_d u_a
+  double uw[5] = {0, 0, 0, 0, 0}, vw[5] = {0, 0, 0, 0, 0};  // u, v at planes p-4 .. p
+  double wi[3][3] = {};  // in-plane vorticity parts at planes p-2, p-1, p
+  for (int p = z0 - 2, buf = 0; p <= z1 + 1; ++p, buf ^= 1) {
+    const long long zo = (long long)wrap(p, g.nz) * g.plane;
+    const bool inside = p >= z0 && p < z1;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double um2[3], um1[3], up1[3], up2[3];
-      vel(q, g.N, wrap_shift(g, id, i, j, k, d, -2), um2);
-      vel(q, g.N, wrap_shift(g, id, i, j, k, d, -1), um1);
-      vel(q, g.N, wrap_shift(g, id, i, j, k, d, +1), up1);
-      vel(q, g.N, wrap_shift(g, id, i, j, k, d, +2), up2);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) G[a][d] = c.c1[d] * (8.0 * (up1[a] - um1[a]) - (up2[a] - um2[a]));
+    for (int l = 0; l < ILOADS; ++l) {
+      const int s = tid + l * kThreads;
+      if (s < IPL) {
+        const long long id = zo + off[l];
+        const double rho = load_as<double>(q[id]);
+        const double m1 = load_as<double>(q[g.N + id]);
+        const double m2 = load_as<double>(q[2 * g.N + id]);
+        const double m3 = load_as<double>(q[3 * g.N + id]);
+        const double u = m1 / rho, v = m2 / rho, w = m3 / rho;
+        vel[buf][0][s] = u;
+        vel[buf][1][s] = v;
+        vel[buf][2][s] = w;
+        if (inside && own[l]) {
+          const double uu = u * u + v * v + w * w;
+          acc[0] += 0.5 * uu;
+          acc[1] += 0.5 * rho * uu;
+          acc[3] += rho;
+          acc[4] += m1;
+          acc[5] += m2;
+          acc[6] += m3;
+          acc[7] += load_as<double>(q[4 * g.N + id]);
+        }
+      }
     }
-    const double w1 = G[2][1] - G[1][2], w2 = G[0][2] - G[2][0], w3 = G[1][0] - G[0][1];
-    acc[0] += 0.5 * uu;
-    acc[1] += 0.5 * rho * uu;
-    acc[2] += w1 * w1 + w2 * w2 + w3 * w3;
+    __syncthreads();  // one barrier per plane: the other buffer is free again
+    const double* U = vel[buf][0];
+    const double* V = vel[buf][1];
+    const double* W = vel[buf][2];
+    const double dxv = c.c1[0] * (8.0 * (V[c0 + 1] - V[c0 - 1]) - (V[c0 + 2] - V[c0 - 2]));
+    const double dxw = c.c1[0] * (8.0 * (W[c0 + 1] - W[c0 - 1]) - (W[c0 + 2] - W[c0 - 2]));
+    const double dyu = c.c1[1] * (8.0 * (U[c0 + IHX] - U[c0 - IHX]) - (U[c0 + 2 * IHX] - U[c0 - 2 * IHX]));
+    const double dyw = c.c1[1] * (8.0 * (W[c0 + IHX] - W[c0 - IHX]) - (W[c0 + 2 * IHX] - W[c0 - 2 * IHX]));
 #pragma unroll
-    for (int f = 0; f < 5; ++f) acc[3 + f] += load_as<double>(q[f * g.N + id]);
+    for (int i = 0; i < 4; ++i) {
+      uw[i] = uw[i + 1];
+      vw[i] = vw[i + 1];
+    }
+    uw[4] = U[c0];
+    vw[4] = V[c0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      wi[0][k] = wi[1][k];
+      wi[1][k] = wi[2][k];
+    }
+    wi[2][0] = dyw;
+    wi[2][1] = -dxw;
+    wi[2][2] = dxv - dyu;
+    // plane p - 2 has its z-neighbours p - 4 .. p in the window now
+    if (p - 2 >= z0 && col_valid) {
+      const double dzu = c.c1[2] * (8.0 * (uw[3] - uw[1]) - (uw[4] - uw[0]));
+      const double dzv = c.c1[2] * (8.0 * (vw[3] - vw[1]) - (vw[4] - vw[0]));
+      const double w1 = wi[0][0] - dzv, w2 = wi[0][1] + dzu, w3 = wi[0][2];
+      acc[2] += w1 * w1 + w2 * w2 + w3 * w3;
+    }
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const double s = block_sum(acc[m], lds);
+    const double s = block_sum(acc[m], red);
     if (threadIdx.x == 0) work[(long long)blockIdx.x * 8 + m] = s;
   }
 }
@@ -110,20 +178,18 @@ __global__ void __launch_bounds__(kThreads) integrals_pass2(long long rows, doub
 
 }  // namespace
 
-long long integrals_blocks(const Grid& g) {
-  const long long per_block = (long long)kThreads * kPointsPerThread;
-  return (g.N + per_block - 1) / per_block;
-}
+long long integrals_blocks(const Grid& g) { return int_launch(g).blocks; }
 
 template <class Tq>
 hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work, double* out8,
                             hipStream_t st) {
-  const long long rows = integrals_blocks(g);
-  hipLaunchKernelGGL((integrals_pass1<Tq>), dim3((unsigned)rows), dim3(kThreads), 0, st, g, c,
-                     static_cast<const Tq*>(q), work);
+  const IntLaunch L = int_launch(g);
+  hipLaunchKernelGGL((integrals_pass1<Tq>), dim3((unsigned)L.blocks), dim3(kThreads), 0, st, g, c,
+                     static_cast<const Tq*>(q), work, L.tiles_x, L.tiles_y, L.kz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(integrals_pass2, dim3(1), dim3(kThreads), 0, st, rows, 1.0 / (double)g.N, c.ire, work, out8);
+  hipLaunchKernelGGL(integrals_pass2, dim3(1), dim3(kThreads), 0, st, L.blocks, 1.0 / (double)g.N, c.ire, work,
+                     out8);
   return hipGetLastError();
 }
 

@@ -30,11 +30,11 @@ import numpy as np  # noqa: E402
 FORMS = ["DP", "SPDP_C64", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"]
 
 
-def run_form(form, n, dt, nsteps, every):
+def run_form(form, n, dt, nsteps, every, mach=0.1):
     import torch
     from paper_2505_20911_amd import tgv
     from paper_2505_20911_amd.solver import TGVSolver
-    p = tgv.Params(n=(n, n, n))
+    p = tgv.Params(n=(n, n, n), mach=mach)
     s = TGVSolver(p, tgv.PRESETS[form])
     s.init()
     torch.cuda.synchronize()
@@ -46,9 +46,9 @@ def run_form(form, n, dt, nsteps, every):
     return q, hist.cpu().numpy(), p.N * 3 * nsteps / (wall * 1e6)
 
 
-def oracle_reference(n, dt, nsteps, every):
+def oracle_reference(n, dt, nsteps, every, mach=0.1):
     import oracle as O
-    p = O.Params(n=(n, n, n))
+    p = O.Params(n=(n, n, n), mach=mach)
     q0 = O.init(p)
     q, hist = O.run(p, dt, nsteps, q0, every=every)
     return q0, q, hist
@@ -70,20 +70,22 @@ def errors(q, hist, q0, qref, href):
     return out
 
 
-def study(n, nsteps, every, forms=FORMS, reference="oracle", dt=None):
+def study(n, nsteps, every, forms=FORMS, reference="oracle", dt=None, mach=0.1):
     dt = dt if dt is not None else 3.7e-3 * 32 / n
     if reference == "oracle":
-        q0, qref, href = oracle_reference(n, dt, nsteps, every)
+        q0, qref, href = oracle_reference(n, dt, nsteps, every, mach)
     else:
         import oracle as O
-        q0 = O.init(O.Params(n=(n, n, n)))
-        qref, href, _ = run_form("DP", n, dt, nsteps, every)
+        q0 = O.init(O.Params(n=(n, n, n), mach=mach))
+        qref, href, _ = run_form("DP", n, dt, nsteps, every, mach)
     res = {}
     for form in forms:
-        q, hist, rate = run_form(form, n, dt, nsteps, every)
+        q, hist, rate = run_form(form, n, dt, nsteps, every, mach)
         res[form] = errors(q, hist, q0, qref, href)
         res[form]["mpt_stage_per_s"] = rate
-    return {"n": n, "steps": nsteps, "every": every, "dt": dt, "reference": reference, "forms": res}
+        print(f"[study] {form} done: max rel eps {res[form]['max_rel_eps']:.2e}, {rate:.0f} Mpt.stage/s",
+              file=sys.stderr, flush=True)
+    return {"n": n, "steps": nsteps, "every": every, "dt": dt, "mach": mach, "reference": reference, "forms": res}
 
 
 def main():
@@ -93,8 +95,10 @@ def main():
     ap.add_argument("--every", type=int, default=10)
     ap.add_argument("--reference", choices=["oracle", "dp"], default="oracle")
     ap.add_argument("--forms", default=",".join(FORMS))
+    ap.add_argument("--dt", type=float, default=None, help="default: 3.7e-3 * 32 / n (constant CFL)")
+    ap.add_argument("--mach", type=float, default=0.1)
     a = ap.parse_args()
-    out = study(a.n, a.steps, a.every, a.forms.split(","), a.reference)
+    out = study(a.n, a.steps, a.every, a.forms.split(","), a.reference, a.dt, a.mach)
     for f, r in out["forms"].items():
         print(f"{f:10s} relL2(dQ) rho {r['rel_l2_dQ'][0]:.2e} E {r['rel_l2_dQ'][4]:.2e}  "
               f"K {r['max_rel_K']:.2e}  eps {r['max_rel_eps']:.2e}  mean|deps| {r['mean_abs_deps']:.2e}  "

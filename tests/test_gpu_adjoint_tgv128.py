@@ -75,3 +75,20 @@ def test_fp32_gradient_close_to_fp64(setup):
     say("FP32 J", float(J), "FP64 J", J64, "gradient rel L2 difference", rel)
     assert abs(float(J) - J64) <= 1e-4 * abs(J64)
     assert rel <= 1e-2
+
+
+def test_fd_step_sits_on_the_plateau(setup):
+    """Central differences along direction 0 for eps = 1e-4 .. 1e-8: the
+    truncation error (O(eps^2)) falls and the rounding error (O(u J / eps))
+    rises; eps = 1e-6 and 1e-5 both sit on the plateau between them."""
+    p, u0, rho0, p0, g, J = setup
+    runner = CheckpointedDissipation(p, tgv.PRESETS["DP"], DT, STEPS, slots=SLOTS)
+    d = torch.from_numpy(S.directions(p.n, 0)).to(DEV)
+    ad = float((g * d).sum())
+    rel = {}
+    for eps in (1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        Jp = runner.forward(state_from_velocity(u0 + eps * d, rho0, p0, p.gamma))
+        Jm = runner.forward(state_from_velocity(u0 - eps * d, rho0, p0, p.gamma))
+        rel[eps] = abs((Jp - Jm) / (2 * eps) - ad) / abs(ad)
+        say(f"eps {eps:.0e}: relative FD - adjoint difference {rel[eps]:.2e}")
+    assert rel[1e-5] <= 1e-6 and rel[1e-6] <= 1e-6
