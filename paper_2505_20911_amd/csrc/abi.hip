@@ -314,7 +314,7 @@ size_t ns_residual_adjoint_workspace_bytes(const ns_params_t* params, const ns_p
   tgv::Grid g;
   bool f64;
   if (check_params(params, &g) || check_adjoint_prec(prec, &f64)) return 0;
-  return (size_t)(6 * g.N) * (f64 ? sizeof(double) : sizeof(float));
+  return (size_t)(tgv::kResidualAdjointWorkFields * g.N) * (f64 ? sizeof(double) : sizeof(float));
 }
 
 int ns_residual_adjoint(const ns_params_t* params, const ns_prec_t* prec, const void* q, const void* r_bar,

@@ -5,9 +5,14 @@
 // D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
 // stencil term of the forward residual turns into a stencil of R_bar-weighted
 // pointwise fields evaluated around the output point, plus pointwise terms.
-// The only coefficient that needs forward derivatives at a neighbour is the
-// adjoint of the viscous work sum tau_ad G_ad, G_bar_ad = 2 R_bar_E tau_ad
-// (symmetric): pass A stores its 6 components, pass B gathers everything.
+// Three passes over a caller-provided workspace of 13 fields:
+//   pass 0 (pointwise) stores the fields the gather needs at stencil
+//     neighbours: u_a, V_bar_a = R_bar_{m_a} + R_bar_E u_a and sum_f R_bar_f Q_f;
+//   pass A stores the adjoint of the viscous work sum tau_ad G_ad, the
+//     symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components; viscous only);
+//   pass B gathers every transposed-stencil and pointwise contribution.
+// 1/rho is the hardware reciprocal refined by Newton-Raphson, as in the
+// forward residual.
 #include "tgv_device.h"
 #include "tgv_kernels.h"
 
@@ -57,14 +62,45 @@ __device__ __forceinline__ int sym(int a, int d) {
   return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
 }
 
+// Workspace layout, fields of N values each.
+enum { W_U = 0, W_VB = 3, W_SRQ = 6, W_GB = 7, W_FIELDS = 13 };
+static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
+
+// Pass 0: pointwise fields read at stencil neighbours by the later passes.
+template <class T>
+__global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict__ q, const T* __restrict__ rb,
+                                                     T* __restrict__ w) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.N) return;
+  const long long N = g.N;
+  T q0[5], r0[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    q0[f] = q[f * N + id];
+    r0[f] = rb[f * N + id];
+  }
+  const T ir = recip(q0[0]);
+  T srq = 0;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) srq += r0[f] * q0[f];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T u = q0[a + 1] * ir;
+    w[(W_U + a) * N + id] = u;
+    w[(W_VB + a) * N + id] = r0[a + 1] + r0[4] * u;
+  }
+  w[W_SRQ * N + id] = srq;
+}
+
 // Pass A: G_bar_ad = 2 R_bar_E tau_ad at every point.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, Coef<T> c, const T* __restrict__ q,
-                                                       const T* __restrict__ rb, T* __restrict__ gbar) {
+__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, Coef<T> c, const T* __restrict__ rb,
+                                                       T* __restrict__ w) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= g.N) return;
   int ijk[3];
   coords(g, id, ijk);
+  const long long N = g.N;
   T G[3][3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -73,28 +109,27 @@ __global__ void __launch_bounds__(kThreads) adj_stress(Grid g, Coef<T> c, const 
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const long long n = nb(g, id, ijk, d, offs[s]);
-      const T ir = T(1) / q[n];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
+      for (int a = 0; a < 3; ++a) u[s][a] = w[(W_U + a) * N + n];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
   }
   const T div = G[0][0] + G[1][1] + G[2][2];
-  const T two_rE = T(2) * rb[4 * g.N + id];
+  const T two_rE = T(2) * rb[4 * N + id];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int d = a; d < 3; ++d) {
       const T tau = c.ire * (G[a][d] + G[d][a] - (a == d ? T(2.0 / 3.0) * div : T(0)));
-      gbar[(long long)sym(a, d) * g.N + id] = two_rE * tau;
+      w[(W_GB + sym(a, d)) * N + id] = two_rE * tau;
     }
 }
 
 // Pass B: gather of all transposed-stencil and pointwise contributions.
 template <class T>
 __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const T* __restrict__ q,
-                                                       const T* __restrict__ rb, const T* __restrict__ gbar,
+                                                       const T* __restrict__ rb, const T* __restrict__ w,
                                                        T* __restrict__ qbar) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= g.N) return;
@@ -109,7 +144,7 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
     q0[f] = q[f * N + id];
     r0[f] = rb[f * N + id];
   }
-  const T ir0 = T(1) / q0[0];
+  const T ir0 = recip(q0[0]);
   T u0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) u0[a] = q0[a + 1] * ir0;
@@ -124,7 +159,7 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
   const int offs[4] = {-2, -1, 1, 2};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    T qn[4][5], rn[4][5], un[4][3], pn[4];
+    T qn[4][5], rn[4][5], un[4][3], sum_rq[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const long long n = nb(g, id, ijk, d, offs[s]);
@@ -133,21 +168,11 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
         qn[s][f] = q[f * N + n];
         rn[s][f] = rb[f * N + n];
       }
-      const T ir = T(1) / qn[s][0];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) un[s][a] = qn[s][a + 1] * ir;
-      pn[s] = c.gm1 * (qn[s][4] - half * (qn[s][1] * un[s][0] + qn[s][2] * un[s][1] + qn[s][3] * un[s][2]));
+      for (int a = 0; a < 3; ++a) un[s][a] = w[(W_U + a) * N + n];
+      sum_rq[s] = w[W_SRQ * N + n];
     }
     const T s1 = c.c1[d], s2 = c.c2[d];
-#define DN(expr_s) D1((expr_s(0)), (expr_s(1)), (expr_s(2)), (expr_s(3)), s1)
-    T sum_rq[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T acc = 0;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) acc += rn[s][f] * qn[s][f];
-      sum_rq[s] = acc;
-    }
     const T dud = D1(un[0][d], un[1][d], un[2][d], un[3][d], s1);  // forward D_d u_d at this point
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
@@ -174,9 +199,9 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
-        const T vb = D2(rn[0][a + 1] + rn[0][4] * un[0][a], rn[1][a + 1] + rn[1][4] * un[1][a],
-                        r0[a + 1] + r0[4] * u0[a], rn[2][a + 1] + rn[2][4] * un[2][a],
-                        rn[3][a + 1] + rn[3][4] * un[3][a], s2);
+        const long long vbase = (long long)(W_VB + a) * N;
+        const T vb = D2(w[vbase + nb(g, id, ijk, d, -2)], w[vbase + nb(g, id, ijk, d, -1)], w[vbase + id],
+                        w[vbase + nb(g, id, ijk, d, 1)], w[vbase + nb(g, id, ijk, d, 2)], s2);
         ub[a] += c.ire * vb;
         if (a == d) ub[a] += c.ire * (T(1.0 / 3.0)) * vb;
         // forward pieces of V_{m_a} at this point
@@ -184,14 +209,13 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
         lap[a] += l;
         if (a == d) X[a] += l;
         // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
-        const long long base = (long long)sym(a, d) * N;
-        ub[a] -= D1(gbar[base + nb(g, id, ijk, d, -2)], gbar[base + nb(g, id, ijk, d, -1)],
-                    gbar[base + nb(g, id, ijk, d, 1)], gbar[base + nb(g, id, ijk, d, 2)], s1);
+        const long long base = (long long)(W_GB + sym(a, d)) * N;
+        ub[a] -= D1(w[base + nb(g, id, ijk, d, -2)], w[base + nb(g, id, ijk, d, -1)],
+                    w[base + nb(g, id, ijk, d, 1)], w[base + nb(g, id, ijk, d, 2)], s1);
       }
       // (8) heat flux
       Tb += c.kap * D2(rn[0][4], rn[1][4], r0[4], rn[2][4], rn[3][4], s2);
     }
-#undef DN
   }
 
   if (c.viscous) {
@@ -213,13 +237,10 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const 
 #pragma unroll
           for (int ib = 0; ib < 4; ++ib) {
             const long long n = nb(g, ida, ijka, b, offs[ib]);
-            const T ir = T(1) / q[n];
-            const T uan = q[(a + 1) * N + n] * ir, ubn = q[(b + 1) * N + n] * ir;
-            const T rE = rb[4 * N + n];
-            ua[ia][ib] = uan;
-            ubb[ia][ib] = ubn;
-            va[ia][ib] = rb[(a + 1) * N + n] + rE * uan;
-            vbb[ia][ib] = rb[(b + 1) * N + n] + rE * ubn;
+            ua[ia][ib] = w[(W_U + a) * N + n];
+            ubb[ia][ib] = w[(W_U + b) * N + n];
+            va[ia][ib] = w[(W_VB + a) * N + n];
+            vbb[ia][ib] = w[(W_VB + b) * N + n];
           }
         }
         T in_ub[4], in_ua[4], in_va[4], in_vb[4];
@@ -290,7 +311,7 @@ __global__ void __launch_bounds__(kThreads) adj_vort(Grid g, Coef<T> c, T scale,
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const long long n = nb(g, id, ijk, d, offs[s]);
-      const T ir = T(1) / q[n];
+      const T ir = recip(q[n]);
 #pragma unroll
       for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
     }
@@ -320,7 +341,7 @@ __global__ void __launch_bounds__(kThreads) adj_curl(Grid g, Coef<T> c, const T*
   ub[0] = d1w(2, 1) - d1w(1, 2);
   ub[1] = d1w(0, 2) - d1w(2, 0);
   ub[2] = d1w(1, 0) - d1w(0, 1);
-  const T ir = T(1) / q[id];
+  const T ir = recip(q[id]);
   T rb = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -339,13 +360,16 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
                                    void* work, hipStream_t st) {
   const T* qq = static_cast<const T*>(q);
   const T* rr = static_cast<const T*>(rbar);
-  T* gb = static_cast<T*>(work);
+  T* w = static_cast<T*>(work);
+  hipLaunchKernelGGL((adj_prim<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, qq, rr, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (c.viscous) {
-    hipLaunchKernelGGL((adj_stress<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, gb);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL((adj_stress<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, rr, w);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((adj_gather<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, gb,
+  hipLaunchKernelGGL((adj_gather<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, w,
                      static_cast<T*>(qbar));
   return hipGetLastError();
 }

@@ -66,6 +66,16 @@ struct Ctx {
   Tc A[5][3];
 };
 
+// Fused stage, forms whose window does not hold Q_in exactly (storage type
+// wider than the arithmetic type, as FP64 Q with FP32 arithmetic): Q_in of
+// the own column in its storage type, read when its plane arrives (the block
+// has just loaded that plane, so the read hits in cache) and kept for the two
+// steps until that plane is emitted.  Slot = window slot of the plane.
+template <class Tq>
+struct QRing {
+  Tq v[5][5];
+};
+
 // Thread-private ring of in-plane partial residuals in LDS: [3 slots][5][NT].
 constexpr int RI_SLOTS = 3;
 
@@ -204,9 +214,12 @@ struct RkArgs {
 // One z-step with the newest plane in window slot PH.
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int PH>
 __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, Ctx<Tc>& cx,
+                                      QRing<Tq>& qr,
                                       Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k, Tc (&nxt)[LOADS][5],
                                       const long long (&off)[LOADS], int p, int kout_lo, int kout_hi,
                                       bool col_valid, long long col_off, int p_last) {
+  // the window holds Q converted exactly to Tc when Tc is at least as wide as Tq
+  constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   const int tid = threadIdx.x;
   const Grid& g = K.g;
   const Coef<Tc>& c = K.c;
@@ -231,6 +244,11 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
     }
   }
   __syncthreads();
+  if (FUSED && !kQinFromWindow && p >= kout_lo && p < kout_hi && col_valid) {
+    const long long id = (long long)p * g.plane + col_off;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qr.v[PH][f] = K.q[f * g.N + id];
+  }
   // prefetch plane p + 1
   if (p < p_last) {
     int z = p + 1;
@@ -341,18 +359,18 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
       } else {
         // Q~ <- A Q~ + dt R ; Q_out <- Q_in + B Q~, with R rounded to its
         // storage type as a stored residual would be.  Q_in at this point is
-        // the window's centre when the arithmetic type is the storage type
-        // (exact), else it is re-read in its storage type.
+        // the window's centre when that holds it exactly, else the register
+        // ring's copy in its storage type.
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
           const Ta rr = load_as<Ta>(store_as<Tr>(Rz[f]));
           const Tqt ts = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f]), rr));
           rk.qt[f * g.N + id] = ts;
           Ta qin;
-          if constexpr (std::is_same<Tq, Tc>::value && std::is_same<Ta, Tc>::value)
+          if constexpr (kQinFromWindow)
             qin = ck[f];
           else
-            qin = load_as<Ta>(K.q[f * g.N + id]);
+            qin = load_as<Ta>(qr.v[K0][f]);
           rk.q_out[f * g.N + id] = store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts)));
         }
       }
@@ -420,19 +438,20 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
     }
   }
   Ctx<Tc> cx;
+  QRing<Tq> qr;
   const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
   // plane p = p_first + t sits in RI slot t % 3; the plane emitted with it,
   // p - 2, in slot (t - 2) % 3 = (t + 1) % 3.
   for (int p = p_first, t = 0; p <= p_last; p += 5, t += 5) {
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 0>(K, rk, cx, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 0>(K, rk, cx, qr, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
     if (p + 1 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 1>(K, rk, cx, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 1>(K, rk, cx, qr, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
     if (p + 2 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 2>(K, rk, cx, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 2>(K, rk, cx, qr, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
     if (p + 3 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 3>(K, rk, cx, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 3>(K, rk, cx, qr, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
     if (p + 4 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 4>(K, rk, cx, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 4>(K, rk, cx, qr, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
   }
 }
 

@@ -31,6 +31,9 @@ template <class Tq>
 hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work,
                             double* out8, hipStream_t st);
 
+// Fields of N values the residual adjoint's workspace holds.
+constexpr int kResidualAdjointWorkFields = 13;
+
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar,
                                    void* qbar, void* work, hipStream_t st);
