@@ -5,11 +5,16 @@
 // D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
 // stencil term of the forward residual turns into a stencil of R_bar-weighted
 // pointwise fields evaluated around the output point, plus pointwise terms.
-// Three passes over a caller-provided workspace of 13 fields:
+// Three passes over a caller-provided workspace of 19 fields:
 //   pass 0 (pointwise) stores the fields the gather needs at stencil
 //     neighbours: u_a, V_bar_a = R_bar_{m_a} + R_bar_E u_a and sum_f R_bar_f Q_f;
-//   pass A stores the adjoint of the viscous work sum tau_ad G_ad, the
-//     symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components; viscous only);
+//   pass A (viscous only) stores the adjoint of the viscous work sum
+//     tau_ad G_ad, the symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components),
+//     and the inner derivatives of the mixed second-derivative terms,
+//     sigma_a = sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a, so
+//     that D_a D_b u_b and (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one
+//     more first difference each in pass B (D_a and D_b commute on the
+//     periodic grid);
 //   pass B gathers every transposed-stencil and pointwise contribution.
 // 1/rho is the hardware reciprocal refined by Newton-Raphson, as in the
 // forward residual.
@@ -46,6 +51,49 @@ __device__ __forceinline__ void coords(const Grid& g, long long id, int ijk[3]) 
   ijk[2] = (int)(id / g.plane);
 }
 
+// Gather kernels walk columns: a block owns a CX x CY tile of (x, y) columns
+// and a chunk of kz planes, x fastest, and each thread loops over its column's
+// planes, so the z-neighbour rows it reads were read by the same block a step
+// or two earlier and the tile's x/y neighbours are shared within the block.
+// Blocks are spread over the 8 XCDs in contiguous runs (hardware block b runs
+// on XCD b mod 8).
+constexpr int CX = 64, CY = kThreads / CX;
+
+struct ColMarch {
+  int tiles_x, tiles_y, kz;
+  long long blocks;
+};
+
+ColMarch col_march(const Grid& g) {
+  ColMarch m;
+  m.tiles_x = (g.nx + CX - 1) / CX;
+  m.tiles_y = (g.ny + CY - 1) / CY;
+  m.kz = 64;
+  while (m.kz > 1 && (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz) < 2048) m.kz /= 2;
+  m.blocks = (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz);
+  return m;
+}
+
+struct Column {
+  int x, y, z0, z1;
+  long long xy;
+  bool valid;
+};
+
+__device__ __forceinline__ Column column(const Grid& g, const ColMarch& m) {
+  const int nb = (int)m.blocks;
+  int b = blockIdx.x;
+  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  Column c;
+  c.x = (b % m.tiles_x) * CX + threadIdx.x % CX;
+  c.y = ((b / m.tiles_x) % m.tiles_y) * CY + threadIdx.x / CX;
+  c.z0 = (b / (m.tiles_x * m.tiles_y)) * m.kz;
+  c.z1 = min(c.z0 + m.kz, g.nz);
+  c.valid = c.x < g.nx && c.y < g.ny;
+  c.xy = (long long)c.y * g.nx + c.x;
+  return c;
+}
+
 template <class T>
 __device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T s) {
   return s * (T(8) * (p1 - m1) - (p2 - m2));
@@ -63,7 +111,7 @@ __device__ __forceinline__ int sym(int a, int d) {
 }
 
 // Workspace layout, fields of N values each.
-enum { W_U = 0, W_VB = 3, W_SRQ = 6, W_GB = 7, W_FIELDS = 13 };
+enum { W_U = 0, W_VB = 3, W_SRQ = 6, W_GB = 7, W_SIG = 13, W_TAU = 16, W_FIELDS = 19 };
 static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 
 // Pass 0: pointwise fields read at stencil neighbours by the later passes.
@@ -92,196 +140,185 @@ __global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict
   w[W_SRQ * N + id] = srq;
 }
 
-// Pass A: G_bar_ad = 2 R_bar_E tau_ad at every point.
+// Pass A: G_bar_ad = 2 R_bar_E tau_ad, sigma_a and tau_b at every point.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, Coef<T> c, const T* __restrict__ rb,
+__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ rb,
                                                        T* __restrict__ w) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
-  int ijk[3];
-  coords(g, id, ijk);
-  const long long N = g.N;
-  T G[3][3];
+  const Column col = column(g, cm);
+  if (!col.valid) return;
+#pragma nounroll
+  for (int z = col.z0; z < col.z1; ++z) {
+    const int ijk[3] = {col.x, col.y, z};
+    const long long id = (long long)z * g.plane + col.xy;
+    const long long N = g.N;
+    T G[3][3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T u[4][3];
-    const int offs[4] = {-2, -1, 1, 2};
+    for (int d = 0; d < 3; ++d) {
+      T u[4][3];
+      const int offs[4] = {-2, -1, 1, 2};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const long long n = nb(g, id, ijk, d, offs[s]);
+      for (int s = 0; s < 4; ++s) {
+        const long long n = nb(g, id, ijk, d, offs[s]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) u[s][a] = w[(W_U + a) * N + n];
+        for (int a = 0; a < 3; ++a) u[s][a] = w[(W_U + a) * N + n];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
     }
+    T dv[3];  // D_a V_bar_a
 #pragma unroll
-    for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
+    for (int a = 0; a < 3; ++a) {
+      const long long base = (long long)(W_VB + a) * N;
+      dv[a] = D1(w[base + nb(g, id, ijk, a, -2)], w[base + nb(g, id, ijk, a, -1)], w[base + nb(g, id, ijk, a, 1)],
+                 w[base + nb(g, id, ijk, a, 2)], c.c1[a]);
+    }
+    w[(W_SIG + 0) * N + id] = G[1][1] + G[2][2];
+    w[(W_SIG + 1) * N + id] = G[0][0] + G[2][2];
+    w[(W_SIG + 2) * N + id] = G[0][0] + G[1][1];
+    w[(W_TAU + 0) * N + id] = dv[1] + dv[2];
+    w[(W_TAU + 1) * N + id] = dv[0] + dv[2];
+    w[(W_TAU + 2) * N + id] = dv[0] + dv[1];
+    const T div = G[0][0] + G[1][1] + G[2][2];
+    const T two_rE = T(2) * rb[4 * N + id];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int d = a; d < 3; ++d) {
+        const T tau = c.ire * (G[a][d] + G[d][a] - (a == d ? T(2.0 / 3.0) * div : T(0)));
+        w[(W_GB + sym(a, d)) * N + id] = two_rE * tau;
+      }
   }
-  const T div = G[0][0] + G[1][1] + G[2][2];
-  const T two_rE = T(2) * rb[4 * N + id];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int d = a; d < 3; ++d) {
-      const T tau = c.ire * (G[a][d] + G[d][a] - (a == d ? T(2.0 / 3.0) * div : T(0)));
-      w[(W_GB + sym(a, d)) * N + id] = two_rE * tau;
-    }
 }
 
 // Pass B: gather of all transposed-stencil and pointwise contributions.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_gather(Grid g, Coef<T> c, const T* __restrict__ q,
+__global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ q,
                                                        const T* __restrict__ rb, const T* __restrict__ w,
                                                        T* __restrict__ qbar) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
-  int ijk[3];
-  coords(g, id, ijk);
-  const long long N = g.N;
-  const T half = T(0.5);
+  const Column col = column(g, cm);
+  if (!col.valid) return;
+#pragma nounroll
+  for (int z = col.z0; z < col.z1; ++z) {
+    const int ijk[3] = {col.x, col.y, z};
+    const long long id = (long long)z * g.plane + col.xy;
+    const long long N = g.N;
+    const T half = T(0.5);
 
-  T q0[5], r0[5];
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    q0[f] = q[f * N + id];
-    r0[f] = rb[f * N + id];
-  }
-  const T ir0 = recip(q0[0]);
-  T u0[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) u0[a] = q0[a + 1] * ir0;
-  const T p0 = c.gm1 * (q0[4] - half * (q0[1] * u0[0] + q0[2] * u0[1] + q0[3] * u0[2]));
-  const T T0 = c.gm2 * p0 * ir0;
-
-  T qb[5] = {0, 0, 0, 0, 0};
-  T ub[3] = {0, 0, 0};
-  T pb = 0, Tb = 0;
-  T lap[3] = {0, 0, 0}, X[3] = {0, 0, 0};  // forward viscous pieces at this point
-
-  const int offs[4] = {-2, -1, 1, 2};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T qn[4][5], rn[4][5], un[4][3], sum_rq[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const long long n = nb(g, id, ijk, d, offs[s]);
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        qn[s][f] = q[f * N + n];
-        rn[s][f] = rb[f * N + n];
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) un[s][a] = w[(W_U + a) * N + n];
-      sum_rq[s] = w[W_SRQ * N + n];
-    }
-    const T s1 = c.c1[d], s2 = c.c2[d];
-    const T dud = D1(un[0][d], un[1][d], un[2][d], un[3][d], s1);  // forward D_d u_d at this point
+    T q0[5], r0[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
-      const T F = half * D1(rn[0][f], rn[1][f], rn[2][f], rn[3][f], s1);
-      qb[f] += F * u0[d];
-      ub[d] += F * q0[f];
-      // (2) u_d D_d q_f
-      qb[f] += half * D1(rn[0][f] * un[0][d], rn[1][f] * un[1][d], rn[2][f] * un[2][d], rn[3][f] * un[3][d], s1);
-      const T dq = D1(qn[0][f], qn[1][f], qn[2][f], qn[3][f], s1);
-      ub[d] -= half * r0[f] * dq;
-      // (3) q_f D_d u_d, pointwise part
-      qb[f] -= half * r0[f] * dud;
+      q0[f] = q[f * N + id];
+      r0[f] = rb[f * N + id];
     }
-    // (3) q_f D_d u_d, stencil part summed over f
-    ub[d] += half * D1(sum_rq[0], sum_rq[1], sum_rq[2], sum_rq[3], s1);
-    // (4) momentum pressure gradient D_d p
-    pb += D1(rn[0][d + 1], rn[1][d + 1], rn[2][d + 1], rn[3][d + 1], s1);
-    // (5) pressure work D_d(p u_d)
-    const T F5 = D1(rn[0][4], rn[1][4], rn[2][4], rn[3][4], s1);
-    pb += F5 * u0[d];
-    ub[d] += F5 * p0;
-    if (c.viscous) {
+    const T ir0 = recip(q0[0]);
+    T u0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u0[a] = q0[a + 1] * ir0;
+    const T p0 = c.gm1 * (q0[4] - half * (q0[1] * u0[0] + q0[2] * u0[1] + q0[3] * u0[2]));
+    const T T0 = c.gm2 * p0 * ir0;
+
+    T qb[5] = {0, 0, 0, 0, 0};
+    T ub[3] = {0, 0, 0};
+    T pb = 0, Tb = 0;
+    T lap[3] = {0, 0, 0}, X[3] = {0, 0, 0};  // forward viscous pieces at this point
+
+    const int offs[4] = {-2, -1, 1, 2};
+    // Neighbour values are consumed one field at a time, and the direction
+    // loop is not unrolled, so that few of them are live at once; the
+    // direction's own components are selected, not indexed.
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      const T u0d = d == 0 ? u0[0] : (d == 1 ? u0[1] : u0[2]);
+      T ubd = 0, Xd = 0;  // contributions to ub[d], X[d]
+      long long n[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) n[s] = nb(g, id, ijk, d, offs[s]);
+      auto at = [&](const T* base, int s) { return base[n[s]]; };
+      auto D1n = [&](const T* base, T sc) { return D1(at(base, 0), at(base, 1), at(base, 2), at(base, 3), sc); };
+      const T s1 = c.c1[d], s2 = c.c2[d];
+      T ud[4];  // u_d at the neighbours
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ud[s] = at(w + (W_U + d) * N, s);
+      const T dud = D1(ud[0], ud[1], ud[2], ud[3], s1);  // forward D_d u_d at this point
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        T rn[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) rn[s] = at(rb + f * N, s);
+        const T Dr = D1(rn[0], rn[1], rn[2], rn[3], s1);
+        // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
+        const T F = half * Dr;
+        qb[f] += F * u0d;
+        ubd += F * q0[f];
+        // (2) u_d D_d q_f
+        qb[f] += half * D1(rn[0] * ud[0], rn[1] * ud[1], rn[2] * ud[2], rn[3] * ud[3], s1);
+        const T dq = D1n(q + f * N, s1);
+        ubd -= half * r0[f] * dq;
+        // (3) q_f D_d u_d, pointwise part
+        qb[f] -= half * r0[f] * dud;
+        // (4) momentum pressure gradient D_d p
+        if (f == d + 1) pb += Dr;
+        if (f == 4) {
+          // (5) pressure work D_d(p u_d)
+          pb += Dr * u0d;
+          ubd += Dr * p0;
+          // (8) heat flux
+          if (c.viscous) Tb += c.kap * D2(rn[0], rn[1], r0[4], rn[2], rn[3], s2);
+        }
+      }
+      // (3) q_f D_d u_d, stencil part summed over f
+      ubd += half * D1n(w + W_SRQ * N, s1);
+      if (c.viscous) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
+          const T* vbase = w + (W_VB + a) * N;
+          const T vb = D2(at(vbase, 0), at(vbase, 1), vbase[id], at(vbase, 2), at(vbase, 3), s2);
+          ub[a] += c.ire * vb;
+          if (a == d) ubd += c.ire * (T(1.0 / 3.0)) * vb;
+          // forward pieces of V_{m_a} at this point
+          const T* ubase = w + (W_U + a) * N;
+          const T l = D2(at(ubase, 0), at(ubase, 1), u0[a], at(ubase, 2), at(ubase, 3), s2);
+          lap[a] += l;
+          if (a == d) Xd += l;
+          // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
+          ub[a] -= D1n(w + (W_GB + sym(a, d)) * N, s1);
+        }
+        // (9) mixed second derivatives through the stored inner differences:
+        //   forward X_d += D_d sigma_d ; adjoint u_d += (1/(3 Re)) D_d tau_d
+        Xd += D1n(w + (W_SIG + d) * N, s1);
+        ubd += c.ire * T(1.0 / 3.0) * D1n(w + (W_TAU + d) * N, s1);
+      }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
-        const long long vbase = (long long)(W_VB + a) * N;
-        const T vb = D2(w[vbase + nb(g, id, ijk, d, -2)], w[vbase + nb(g, id, ijk, d, -1)], w[vbase + id],
-                        w[vbase + nb(g, id, ijk, d, 1)], w[vbase + nb(g, id, ijk, d, 2)], s2);
-        ub[a] += c.ire * vb;
-        if (a == d) ub[a] += c.ire * (T(1.0 / 3.0)) * vb;
-        // forward pieces of V_{m_a} at this point
-        const T l = D2(un[0][a], un[1][a], u0[a], un[2][a], un[3][a], s2);
-        lap[a] += l;
-        if (a == d) X[a] += l;
-        // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
-        const long long base = (long long)(W_GB + sym(a, d)) * N;
-        ub[a] -= D1(w[base + nb(g, id, ijk, d, -2)], w[base + nb(g, id, ijk, d, -1)],
-                    w[base + nb(g, id, ijk, d, 1)], w[base + nb(g, id, ijk, d, 2)], s1);
+        ub[a] += a == d ? ubd : T(0);
+        X[a] += a == d ? Xd : T(0);
       }
-      // (8) heat flux
-      Tb += c.kap * D2(rn[0][4], rn[1][4], r0[4], rn[2][4], rn[3][4], s2);
     }
-  }
 
-  if (c.viscous) {
-    // Mixed derivatives on each coordinate plane (a, b).
+    if (c.viscous) {
+      // pointwise part of sum_a u_a V_{m_a}
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = a + 1; b < 3; ++b) {
-        T ua[4][4], ubb[4][4], va[4][4], vbb[4][4];
-#pragma unroll
-        for (int ia = 0; ia < 4; ++ia) {
-          const long long ida = nb(g, id, ijk, a, offs[ia]);
-          int ijka[3] = {ijk[0], ijk[1], ijk[2]};
-          const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-          int t = ijka[a] + offs[ia];
-          t += (t < 0) ? na : 0;
-          t -= (t >= na) ? na : 0;
-          ijka[a] = t;
-#pragma unroll
-          for (int ib = 0; ib < 4; ++ib) {
-            const long long n = nb(g, ida, ijka, b, offs[ib]);
-            ua[ia][ib] = w[(W_U + a) * N + n];
-            ubb[ia][ib] = w[(W_U + b) * N + n];
-            va[ia][ib] = w[(W_VB + a) * N + n];
-            vbb[ia][ib] = w[(W_VB + b) * N + n];
-          }
-        }
-        T in_ub[4], in_ua[4], in_va[4], in_vb[4];
-#pragma unroll
-        for (int ia = 0; ia < 4; ++ia) {
-          in_ub[ia] = D1(ubb[ia][0], ubb[ia][1], ubb[ia][2], ubb[ia][3], c.c1[b]);
-          in_va[ia] = D1(va[ia][0], va[ia][1], va[ia][2], va[ia][3], c.c1[b]);
-        }
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-          in_ua[ib] = D1(ua[0][ib], ua[1][ib], ua[2][ib], ua[3][ib], c.c1[a]);
-          in_vb[ib] = D1(vbb[0][ib], vbb[1][ib], vbb[2][ib], vbb[3][ib], c.c1[a]);
-        }
-        // forward: X_a += D_a D_b u_b, X_b += D_b D_a u_a
-        X[a] += D1(in_ub[0], in_ub[1], in_ub[2], in_ub[3], c.c1[a]);
-        X[b] += D1(in_ua[0], in_ua[1], in_ua[2], in_ua[3], c.c1[b]);
-        // adjoint: u_b += (1/(3 Re)) D_a D_b V_bar_a ; u_a += (1/(3 Re)) D_b D_a V_bar_b
-        ub[b] += c.ire * T(1.0 / 3.0) * D1(in_va[0], in_va[1], in_va[2], in_va[3], c.c1[a]);
-        ub[a] += c.ire * T(1.0 / 3.0) * D1(in_vb[0], in_vb[1], in_vb[2], in_vb[3], c.c1[b]);
-      }
-    // pointwise part of sum_a u_a V_{m_a}
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ub[a] += r0[4] * (c.ire * (lap[a] + X[a] * T(1.0 / 3.0)));
-  }
+      for (int a = 0; a < 3; ++a) ub[a] += r0[4] * (c.ire * (lap[a] + X[a] * T(1.0 / 3.0)));
+    }
 
-  // Chain through the primitive variables at this point.
-  pb += c.gm2 * Tb * ir0;
-  qb[0] -= T0 * Tb * ir0;
-  qb[4] += c.gm1 * pb;
+    // Chain through the primitive variables at this point.
+    pb += c.gm2 * Tb * ir0;
+    qb[0] -= T0 * Tb * ir0;
+    qb[4] += c.gm1 * pb;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    qb[a + 1] -= half * c.gm1 * pb * u0[a];
-    ub[a] -= half * c.gm1 * pb * q0[a + 1];
+    for (int a = 0; a < 3; ++a) {
+      qb[a + 1] -= half * c.gm1 * pb * u0[a];
+      ub[a] -= half * c.gm1 * pb * q0[a + 1];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qb[a + 1] += ub[a] * ir0;
+      qb[0] -= ub[a] * u0[a] * ir0;
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qbar[f * N + id] += qb[f];
   }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    qb[a + 1] += ub[a] * ir0;
-    qb[0] -= ub[a] * u0[a] * ir0;
-  }
-#pragma unroll
-  for (int f = 0; f < 5; ++f) qbar[f * N + id] += qb[f];
 }
 
 // Reversed RK stage: zeta += B q_bar ; r_bar = dt zeta ; zeta = A zeta.
@@ -297,58 +334,64 @@ __global__ void __launch_bounds__(kThreads) rk_adj(long long n5, T A, T B, T dt,
 
 // eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_vort(Grid g, Coef<T> c, T scale, const T* __restrict__ q,
+__global__ void __launch_bounds__(kThreads) adj_vort(Grid g, ColMarch cm, Coef<T> c, T scale, const T* __restrict__ q,
                                                      T* __restrict__ wbar) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
-  int ijk[3];
-  coords(g, id, ijk);
-  T G[3][3];
-  const int offs[4] = {-2, -1, 1, 2};
+  const Column col = column(g, cm);
+  if (!col.valid) return;
+#pragma nounroll
+  for (int z = col.z0; z < col.z1; ++z) {
+    const int ijk[3] = {col.x, col.y, z};
+    const long long id = (long long)z * g.plane + col.xy;
+    T G[3][3];
+    const int offs[4] = {-2, -1, 1, 2};
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T u[4][3];
+    for (int d = 0; d < 3; ++d) {
+      T u[4][3];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const long long n = nb(g, id, ijk, d, offs[s]);
-      const T ir = recip(q[n]);
+      for (int s = 0; s < 4; ++s) {
+        const long long n = nb(g, id, ijk, d, offs[s]);
+        const T ir = recip(q[n]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
+        for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
+    wbar[id] = scale * (G[2][1] - G[1][2]);
+    wbar[g.N + id] = scale * (G[0][2] - G[2][0]);
+    wbar[2 * g.N + id] = scale * (G[1][0] - G[0][1]);
   }
-  wbar[id] = scale * (G[2][1] - G[1][2]);
-  wbar[g.N + id] = scale * (G[0][2] - G[2][0]);
-  wbar[2 * g.N + id] = scale * (G[1][0] - G[0][1]);
 }
 
 // eps^S adjoint pass B: u_bar = curl_D(omega_bar), then through u = m / rho.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_curl(Grid g, Coef<T> c, const T* __restrict__ q,
+__global__ void __launch_bounds__(kThreads) adj_curl(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ q,
                                                      const T* __restrict__ wbar, T* __restrict__ qbar) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
-  int ijk[3];
-  coords(g, id, ijk);
-  const long long N = g.N;
-  auto d1w = [&](int comp, int d) {
-    const T* w = wbar + comp * N;
-    return D1(w[nb(g, id, ijk, d, -2)], w[nb(g, id, ijk, d, -1)], w[nb(g, id, ijk, d, 1)],
-              w[nb(g, id, ijk, d, 2)], c.c1[d]);
-  };
-  T ub[3];
-  ub[0] = d1w(2, 1) - d1w(1, 2);
-  ub[1] = d1w(0, 2) - d1w(2, 0);
-  ub[2] = d1w(1, 0) - d1w(0, 1);
-  const T ir = recip(q[id]);
-  T rb = 0;
+  const Column col = column(g, cm);
+  if (!col.valid) return;
+#pragma nounroll
+  for (int z = col.z0; z < col.z1; ++z) {
+    const int ijk[3] = {col.x, col.y, z};
+    const long long id = (long long)z * g.plane + col.xy;
+    const long long N = g.N;
+    auto d1w = [&](int comp, int d) {
+      const T* w = wbar + comp * N;
+      return D1(w[nb(g, id, ijk, d, -2)], w[nb(g, id, ijk, d, -1)], w[nb(g, id, ijk, d, 1)],
+                w[nb(g, id, ijk, d, 2)], c.c1[d]);
+    };
+    T ub[3];
+    ub[0] = d1w(2, 1) - d1w(1, 2);
+    ub[1] = d1w(0, 2) - d1w(2, 0);
+    ub[2] = d1w(1, 0) - d1w(0, 1);
+    const T ir = recip(q[id]);
+    T rb = 0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    qbar[(a + 1) * N + id] += ub[a] * ir;
-    rb -= ub[a] * q[(a + 1) * N + id] * ir * ir;
+    for (int a = 0; a < 3; ++a) {
+      qbar[(a + 1) * N + id] += ub[a] * ir;
+      rb -= ub[a] * q[(a + 1) * N + id] * ir * ir;
+    }
+    qbar[id] += rb;
   }
-  qbar[id] += rb;
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -361,15 +404,16 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* qq = static_cast<const T*>(q);
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
+  const ColMarch cm = col_march(g);
   hipLaunchKernelGGL((adj_prim<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, qq, rr, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (c.viscous) {
-    hipLaunchKernelGGL((adj_stress<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, rr, w);
+    hipLaunchKernelGGL((adj_stress<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, rr, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((adj_gather<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, qq, rr, w,
+  hipLaunchKernelGGL((adj_gather<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, qq, rr, w,
                      static_cast<T*>(qbar));
   return hipGetLastError();
 }
@@ -389,11 +433,12 @@ template <class T>
 hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void* q, double eps_bar, void* qbar,
                                     void* work, hipStream_t st) {
   const T scale = (T)(eps_bar * 2.0 / ((double)g.N) * (double)c.ire);
-  hipLaunchKernelGGL((adj_vort<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, scale,
+  const ColMarch cm = col_march(g);
+  hipLaunchKernelGGL((adj_vort<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, scale,
                      static_cast<const T*>(q), static_cast<T*>(work));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((adj_curl<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, c, static_cast<const T*>(q),
+  hipLaunchKernelGGL((adj_curl<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, static_cast<const T*>(q),
                      static_cast<const T*>(work), static_cast<T*>(qbar));
   return hipGetLastError();
 }

@@ -30,11 +30,11 @@ import numpy as np  # noqa: E402
 FORMS = ["DP", "SPDP_C64", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"]
 
 
-def run_form(form, n, dt, nsteps, every, mach=0.1):
+def run_form(form, n, dt, nsteps, every, mach=0.1, reynolds=1600.0):
     import torch
     from paper_2505_20911_amd import tgv
     from paper_2505_20911_amd.solver import TGVSolver
-    p = tgv.Params(n=(n, n, n), mach=mach)
+    p = tgv.Params(n=(n, n, n), mach=mach, reynolds=reynolds)
     s = TGVSolver(p, tgv.PRESETS[form])
     s.init()
     torch.cuda.synchronize()
