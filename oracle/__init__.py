@@ -68,6 +68,16 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+# Split forms of the convective term (Sec. 2.3.1 and the inviscid comparison of
+# Sec. 4.2), by the value of Params.split.
+SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4}
+
+
+def _blaisdell_only(P, what):
+    if P.split != 0:
+        raise ValueError(f"{what} is written for the Blaisdell split form only")
+
+
 @dataclass
 class Params:
     """Physical and grid parameters (Sec. 4.1).  n = (nx, ny, nz)."""
@@ -78,10 +88,11 @@ class Params:
     re: float = 1600.0
     pr: float = 0.71
     viscous: int = 1
+    split: int = 0  # convective split form, SPLIT_FORMS
 
     def packed(self) -> np.ndarray:
         return np.array(list(self.n) + list(self.L) +
-                        [self.gamma, self.mach, self.re, self.pr, float(self.viscous)],
+                        [self.gamma, self.mach, self.re, self.pr, float(self.viscous), float(self.split)],
                         dtype=np.float64)
 
     @property
@@ -129,6 +140,7 @@ def residual_c(P: Params, q) -> np.ndarray:
 
 def residual_adjoint(P: Params, q, rbar, qbar=None) -> np.ndarray:
     """qbar += (dR/dQ)^T rbar (hand-written reverse mode of ``residual``)."""
+    _blaisdell_only(P, "residual_adjoint")
     q = _q(P, q)
     rbar = _q(P, rbar)
     if qbar is None:
@@ -232,6 +244,7 @@ def dissipation_c(P: Params, dt: float, nsteps: int, q0) -> complex:
 
 def dissipation_grad(P: Params, dt: float, nsteps: int, q0):
     """(J, dJ/dQ^0) by store-all reverse mode through the RK3 stages."""
+    _blaisdell_only(P, "dissipation_grad")
     q0 = _q(P, q0)
     J = np.zeros(1, np.float64)
     g = np.zeros_like(q0)
@@ -257,6 +270,7 @@ def velocity_grad_from_state_grad(P: Params, qbar0: np.ndarray, u0: np.ndarray,
 
 def residual_at(P: Params, q, idx) -> np.ndarray:
     """Residual at the listed linear point indices (pointwise evaluation), shape (len(idx), 5)."""
+    _blaisdell_only(P, "residual_at")
     q = _q(P, q)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     out = np.empty((idx.size, 5), np.float64)

@@ -47,19 +47,41 @@ class Ops:
         return self._apply(self.D2[axis], f, axis)
 
 
-def residual(q, n, L, gamma, mach, re, pr, viscous=True):
+SPLIT = ("blaisdell", "divergence", "feiereisen", "jameson", "kgp")
+
+
+def _pair(ops, A, B, d):
+    """Quadratic split of D(A B): 1/2 [D(A B) + A D(B) + B D(A)]."""
+    return 0.5 * (ops.d1(A * B, d) + A * ops.d1(B, d) + B * ops.d1(A, d))
+
+
+def convective(ops, rho, u, phi, d, split):
+    """Split form of D_d(rho u_d phi) by its pairing of the three factors;
+    the cubic Kennedy-Gruber-Pirozzoli form through its identity with the
+    pairings, KGP = (Blaisdell + Feiereisen + Jameson) / 2 - divergence / 2."""
+    if split == "divergence":
+        return ops.d1(rho * u[d] * phi, d)
+    if split == "blaisdell":
+        return _pair(ops, rho * phi, u[d], d)
+    if split == "feiereisen":
+        return _pair(ops, rho * u[d], phi, d)
+    if split == "jameson":
+        return _pair(ops, rho, u[d] * phi, d)
+    return 0.5 * (_pair(ops, rho * phi, u[d], d) + _pair(ops, rho * u[d], phi, d)
+                  + _pair(ops, rho, u[d] * phi, d)) - 0.5 * ops.d1(rho * u[d] * phi, d)
+
+
+def residual(q, n, L, gamma, mach, re, pr, viscous=True, split="blaisdell"):
     """R = -C - P + V for Q = (rho, m1, m2, m3, rho E) shaped (5, nz, ny, nx)."""
     ops = Ops(n, L)
     rho, m, E = q[0], [q[1], q[2], q[3]], q[4]
     u = [m[a] / rho for a in range(3)]
     p = (gamma - 1.0) * (E - 0.5 * (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]))
     T = gamma * mach ** 2 * p / rho
-    cons = [rho, m[0], m[1], m[2], E]
+    phis = [np.ones_like(rho), u[0], u[1], u[2], E / rho]
     R = np.zeros_like(q)
-    for f, qf in enumerate(cons):
-        C = sum(0.5 * (ops.d1(qf * u[d], d) + u[d] * ops.d1(qf, d) + qf * ops.d1(u[d], d))
-                for d in range(3))
-        R[f] -= C
+    for f, phi in enumerate(phis):
+        R[f] -= sum(convective(ops, rho, u, phi, d, split) for d in range(3))
     for a in range(3):
         R[a + 1] -= ops.d1(p, a)
     R[4] -= sum(ops.d1(p * u[d], d) for d in range(3))

@@ -25,6 +25,12 @@
 //   * Blaisdell split of the convective term d(rho u_j phi)/dx_j with the pairing
 //     (rho phi) x (u_j):  1/2 [ D(rho phi u_j) + u_j D(rho phi) + rho phi D(u_j) ],
 //     applied to phi = 1, u_i, E (Sec. 2.3.1, convective form equation);
+//     the other split forms the paper compares in the inviscid limit (Sec. 4.2),
+//     selected by `split`: divergence D(rho u_j phi); Feiereisen (printed in
+//     Sec. 2.3.1), pairing (rho u_j) x (phi); Jameson, pairing (rho) x (u_j phi);
+//     Kennedy-Gruber-Pirozzoli, the cubic split averaging the divergence form
+//     and all six product-rule expansions of the triple product (weights 1/4);
+//     phi = E is the specific total energy (rho E)/rho;
 //   * pressure terms in divergence form, not split;
 //   * constant viscosity mu = 1, Stokes stress, Fourier heat flux with
 //     kappa = 1/((gamma-1) M^2 Pr Re), T = gamma M^2 p / rho (equation of state
@@ -48,6 +54,7 @@ struct Params {
   double L[3];
   double gamma, mach, re, pr;
   int viscous;
+  int split;  // 0 Blaisdell, 1 divergence, 2 Feiereisen, 3 Jameson, 4 KGP
 };
 
 Params unpack(const double* pv) {
@@ -59,6 +66,7 @@ Params unpack(const double* pv) {
   P.re = pv[8];
   P.pr = pv[9];
   P.viscous = (int)pv[10];
+  P.split = (int)pv[11];
   return P;
 }
 
@@ -228,17 +236,56 @@ void residual(const Params& P, const S* q, S* r) {
   Prim<S> w = primitives(P, q);
   const Field<S>* cons[5] = {&w.rho, &w.m[0], &w.m[1], &w.m[2], &w.E};
 
-  // Convection, Blaisdell split: C_q = 1/2 sum_d [D_d(q u_d) + u_d D_d q + q D_d u_d].
+  // Convection C_q for q = rho phi, phi in (1, u_1, u_2, u_3, E/rho).
   Field<S> C[5];
   Field<S> Du[3];
   for (int d = 0; d < 3; ++d) Du[d] = D1(P, w.u[d], d);  // D_d u_d
-  for (int f = 0; f < 5; ++f) {
-    C[f].assign(N, S(0.0));
-    for (int d = 0; d < 3; ++d) {
-      Field<S> t1 = D1(P, mul(*cons[f], w.u[d]), d);
-      Field<S> t2 = mul(w.u[d], D1(P, *cons[f], d));
-      Field<S> t3 = mul(*cons[f], Du[d]);
-      for (long i = 0; i < N; ++i) C[f][i] += 0.5 * (t1[i] + t2[i] + t3[i]);
+  if (P.split == 0) {
+    // Blaisdell: C_q = 1/2 sum_d [D_d(q u_d) + u_d D_d q + q D_d u_d].
+    for (int f = 0; f < 5; ++f) {
+      C[f].assign(N, S(0.0));
+      for (int d = 0; d < 3; ++d) {
+        Field<S> t1 = D1(P, mul(*cons[f], w.u[d]), d);
+        Field<S> t2 = mul(w.u[d], D1(P, *cons[f], d));
+        Field<S> t3 = mul(*cons[f], Du[d]);
+        for (long i = 0; i < N; ++i) C[f][i] += 0.5 * (t1[i] + t2[i] + t3[i]);
+      }
+    }
+  } else {
+    // The seven terms the other forms combine, for direction d:
+    //   t_div  = D(rho u phi)      t_uDq  = u D(rho phi)    t_qDu   = rho phi D(u)
+    //   t_phDm = phi D(rho u)      t_mDph = rho u D(phi)
+    //   t_rDuf = rho D(u phi)      t_ufDr = u phi D(rho)
+    Field<S> phi[5];
+    phi[0].assign(N, S(1.0));
+    for (int a = 0; a < 3; ++a) phi[a + 1] = w.u[a];
+    phi[4].resize(N);
+    for (long i = 0; i < N; ++i) phi[4][i] = w.E[i] / w.rho[i];
+    Field<S> Drho[3];
+    for (int d = 0; d < 3; ++d) Drho[d] = D1(P, w.rho, d);
+    for (int f = 0; f < 5; ++f) {
+      C[f].assign(N, S(0.0));
+      for (int d = 0; d < 3; ++d) {
+        Field<S> t_div = D1(P, mul(*cons[f], w.u[d]), d);
+        Field<S> t_uDq = mul(w.u[d], D1(P, *cons[f], d));
+        Field<S> t_qDu = mul(*cons[f], Du[d]);
+        Field<S> t_phDm = mul(phi[f], D1(P, w.m[d], d));
+        Field<S> t_mDph = mul(w.m[d], D1(P, phi[f], d));
+        Field<S> t_rDuf = mul(w.rho, D1(P, mul(w.u[d], phi[f]), d));
+        Field<S> t_ufDr = mul(mul(w.u[d], phi[f]), Drho[d]);
+        for (long i = 0; i < N; ++i) {
+          S c;
+          if (P.split == 1)
+            c = t_div[i];
+          else if (P.split == 2)
+            c = 0.5 * (t_div[i] + t_phDm[i] + t_mDph[i]);
+          else if (P.split == 3)
+            c = 0.5 * (t_div[i] + t_rDuf[i] + t_ufDr[i]);
+          else
+            c = 0.25 * (t_div[i] + t_rDuf[i] + t_uDq[i] + t_phDm[i] + t_mDph[i] + t_qDu[i] + t_ufDr[i]);
+          C[f][i] += c;
+        }
+      }
     }
   }
 

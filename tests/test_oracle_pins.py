@@ -245,6 +245,96 @@ def test_residual_matches_dense_brute_force_tgv_and_random():
             assert np.all(err <= 1e-15 * term_scale(p, q)), (err, term_scale(p, q))
 
 
+# --------------------------------------------------------------------------
+# Split forms of the convective term (Sec. 2.3.1; inviscid comparison, Sec. 4.2)
+# --------------------------------------------------------------------------
+
+SPLITS = list(O.SPLIT_FORMS.items())
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+def test_split_form_matches_dense_brute_force(name, split):
+    """The brute force builds each form from its pairing of the factors
+    rho, u_j, phi (and KGP from its identity with the three pairings), not from
+    the oracle's term list."""
+    p = P((12, 10, 8), split=split)
+    for q in (O.init(p), S.random_state(p.n, 31, smooth=True), S.random_state(p.n, 32)):
+        for visc in (1, 0):
+            p.viscous = visc
+            r = O.residual(p, q)
+            rb = brute.residual(q, p.n, p.L, p.gamma, p.mach, p.re, p.pr, bool(visc), name)
+            err = np.abs(r - rb).reshape(5, -1).max(axis=1)
+            assert np.all(err <= 1e-15 * term_scale(p, q)), (name, err)
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+def test_split_form_converges_to_continuous_equations(name, split):
+    """Every split form is a consistent discretisation of the same equations:
+    4th-order convergence to the spectral conservative-form right-hand side
+    (inviscid, M = 0.5 so pressure and convection are both O(1))."""
+    gamma, mach = 1.4, 0.5
+    nf = 128
+    _, _, _, rho_f, u_f = analytic_state(nf)
+    z, y, x = np.meshgrid(*(np.arange(m) * 2 * np.pi / m for m in (nf, nf, nf)), indexing="ij")
+    p_f = (1.0 / (gamma * mach ** 2)) * (1.0 + 0.1 * np.cos(x + z) + 0.05 * np.sin(2 * y))
+    Rref_f = spectral_residual(rho_f, u_f, p_f, gamma, mach, 10.0, 0.71, False)
+    errs = []
+    for n in (16, 32, 64):
+        s = nf // n
+        rho, u, pp = rho_f[::s, ::s, ::s], [uu[::s, ::s, ::s] for uu in u_f], p_f[::s, ::s, ::s]
+        q = np.empty((5, n, n, n))
+        q[0] = rho
+        for a in range(3):
+            q[a + 1] = rho * u[a]
+        q[4] = pp / (gamma - 1) + 0.5 * rho * sum(uu ** 2 for uu in u)
+        R = O.residual(P(n, gamma=gamma, mach=mach, viscous=0, split=split), q)
+        errs.append(np.abs(R - Rref_f[:, ::s, ::s, ::s]).reshape(5, -1).max(axis=1))
+    errs = np.array(errs)
+    for f in range(5):
+        order = math.log2(errs[1, f] / errs[2, f])
+        assert 3.7 < order < 4.4, (name, f, errs[:, f])
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+def test_split_form_conserves_and_vanishes_on_uniform_states(name, split):
+    """D1 is skew and its columns sum to zero, so every product-rule pair
+    (a D b + b D a) and every divergence sums to zero over the periodic grid:
+    mass, momentum and (inviscid) total energy are conserved by every form.
+    A uniform state has zero residual in every form."""
+    p = P((12, 16, 10), viscous=0, split=split)
+    q = S.random_state(p.n, 21)
+    r = O.residual(p, q).reshape(5, -1)
+    for f in range(5):
+        assert abs(r[f].sum()) < 1e-13 * np.abs(r[f]).sum(), (name, f)
+    qu = np.empty(p.shape)
+    qu[0] = 1.3
+    for a, U in enumerate((0.2, -0.4, 0.1)):
+        qu[a + 1] = 1.3 * U
+    qu[4] = 50.0 / 0.4 + 0.5 * 1.3 * 0.21
+    h = min(p.h(d) for d in range(3))
+    assert np.abs(O.residual(p, qu)).max() < 1e-14 * np.abs(qu).max() / h ** 2
+
+
+def test_split_forms_relations():
+    """Exact relations between the forms: for phi = 1 (continuity) Feiereisen
+    is the divergence form and Jameson and KGP are Blaisdell; and the cubic
+    KGP form is (Blaisdell + Feiereisen + Jameson)/2 - divergence/2 for every
+    component (the pressure and viscous terms, common to all, cancel)."""
+    q = S.random_state((12, 10, 8), 41, smooth=True)
+    R = {name: O.residual(P((12, 10, 8), split=k), q) for name, k in SPLITS}
+    sc = term_scale(P((12, 10, 8)), q)
+    close = lambda a, b, f: np.abs(a - b).max() <= 1e-14 * sc[f]
+    assert close(R["feiereisen"][0], R["divergence"][0], 0)
+    assert close(R["jameson"][0], R["blaisdell"][0], 0)
+    assert close(R["kgp"][0], R["blaisdell"][0], 0)
+    comb = 0.5 * (R["blaisdell"] + R["feiereisen"] + R["jameson"]) - 0.5 * R["divergence"]
+    for f in range(5):
+        assert close(R["kgp"][f], comb[f], f), f
+    # and the forms do differ where phi varies (by their truncation errors)
+    for a, b in (("feiereisen", "blaisdell"), ("jameson", "blaisdell"), ("divergence", "kgp")):
+        assert np.abs(R[a][1] - R[b][1]).max() > 1e-4 * np.abs(R[b][1]).max(), (a, b)
+
+
 def test_residual_pointwise_matches_whole_field():
     p = P((12, 16, 20))
     q = S.random_state(p.n, 5)
