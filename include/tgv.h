@@ -54,6 +54,26 @@ extern "C" {
 
 typedef enum { NS_F64 = 0, NS_F32 = 1, NS_F16 = 2, NS_BF16 = 3 } ns_dtype_t;
 
+/* Split form of the convective term d(rho u_j phi)/dx_j, phi = (1, u_i, E)
+ * (Sec. 2.3.1; the forms the paper compares in the inviscid limit, Sec. 4.2).
+ * D is the 4th-order central first difference.
+ *   BLAISDELL  (rho phi) x (u_j):  [D(rho phi u_j) + u_j D(rho phi) + rho phi D(u_j)] / 2
+ *   DIVERGENCE D(rho u_j phi)
+ *   FEIEREISEN (rho u_j) x (phi):  [D(rho u_j phi) + phi D(rho u_j) + rho u_j D(phi)] / 2
+ *   JAMESON    (rho) x (u_j phi):  [D(rho u_j phi) + rho D(u_j phi) + u_j phi D(rho)] / 2
+ *   KGP        Kennedy-Gruber-Pirozzoli cubic form: the divergence term and
+ *              the six product-rule expansions of the triple product, each / 4.
+ * The pressure terms stay in divergence form in every variant.  Forms other
+ * than BLAISDELL are available in the DP and HPSP precision forms, and the
+ * adjoint supports BLAISDELL only (NS_ERR_ARG otherwise). */
+typedef enum {
+  NS_SPLIT_BLAISDELL = 0,
+  NS_SPLIT_DIVERGENCE = 1,
+  NS_SPLIT_FEIEREISEN = 2,
+  NS_SPLIT_JAMESON = 3,
+  NS_SPLIT_KGP = 4
+} ns_split_t;
+
 typedef struct {
   int32_t n[3];     /* nx, ny, nz */
   double L[3];      /* box lengths (2 pi for the Taylor-Green vortex) */
@@ -62,6 +82,7 @@ typedef struct {
   double reynolds;  /* Reynolds number Re */
   double prandtl;   /* Prandtl number Pr */
   int32_t viscous;  /* 1: full equations; 0: diffusive terms omitted (inviscid variant, Sec. 4.2) */
+  int32_t split;    /* ns_split_t; only the residual entry points read it */
 } ns_params_t;
 
 typedef struct {

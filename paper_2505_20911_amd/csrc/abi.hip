@@ -71,6 +71,8 @@ int check_params(const ns_params_t* p, tgv::Grid* g) {
   if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) return fail(NS_ERR_ARG, "gamma must be finite and > 1");
   if (!finite_pos(p->mach)) return fail(NS_ERR_ARG, "mach must be finite and > 0");
   if (p->viscous != 0 && p->viscous != 1) return fail(NS_ERR_ARG, "viscous must be 0 or 1");
+  if (p->split < NS_SPLIT_BLAISDELL || p->split > NS_SPLIT_KGP)
+    return fail(NS_ERR_ARG, "split must be one of NS_SPLIT_BLAISDELL .. NS_SPLIT_KGP");
   if (!finite_pos(p->reynolds)) return fail(NS_ERR_ARG, "reynolds must be finite and > 0");
   if (!finite_pos(p->prandtl)) return fail(NS_ERR_ARG, "prandtl must be finite and > 0");
   g->nx = p->n[0];
@@ -129,11 +131,24 @@ tgv::Coef<Tc> make_coef(const ns_params_t* p) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Split forms other than Blaisdell are built for the DP and HPSP forms.
+int check_split(const ns_params_t* p, Form f) {
+  if (p->split != NS_SPLIT_BLAISDELL && f != DP && f != HPSP)
+    return fail(NS_ERR_ARG, "split forms other than Blaisdell are available for the DP and HPSP precision forms");
+  return NS_OK;
+}
+
+// The adjoint is written for the Blaisdell split form.
+int check_adjoint_split(const ns_params_t* p) {
+  if (p->split != NS_SPLIT_BLAISDELL) return fail(NS_ERR_ARG, "the adjoint supports the Blaisdell split form only");
+  return NS_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int tgv_abi_version(void) { return 1; }
+int tgv_abi_version(void) { return 2; }
 
 const char* ns_last_error(void) { return g_err.c_str(); }
 
@@ -158,7 +173,7 @@ int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q,
   Form f;
   int rc = check_params(params, &g);
   if (rc) return rc;
-  if ((rc = check_prec(prec, &f))) return rc;
+  if ((rc = check_prec(prec, &f)) || (rc = check_split(params, f))) return rc;
   if ((rc = check_ptr(q, "q")) || (rc = check_ptr(r, "r"))) return rc;
   if (q == r) return fail(NS_ERR_ARG, "q and r must not overlap");
   hipStream_t st = as_stream(stream);
@@ -166,14 +181,14 @@ int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q,
   using tgv::bf16;
   using tgv::f16;
   switch (f) {
-    case DP: e = tgv::launch_residual<double, double, double>(g, make_coef<double>(params), q, r, st); break;
-    case SPDP: e = tgv::launch_residual<double, float, float>(g, make_coef<float>(params), q, r, st); break;
-    case SPDP_C64: e = tgv::launch_residual<double, float, double>(g, make_coef<double>(params), q, r, st); break;
-    case SP_DPC: e = tgv::launch_residual<float, float, double>(g, make_coef<double>(params), q, r, st); break;
-    case SP: e = tgv::launch_residual<float, float, float>(g, make_coef<float>(params), q, r, st); break;
-    case HPSP: e = tgv::launch_residual<float, f16, float>(g, make_coef<float>(params), q, r, st); break;
-    case HPSP_BF16: e = tgv::launch_residual<float, bf16, float>(g, make_coef<float>(params), q, r, st); break;
-    case HP: e = tgv::launch_residual<f16, f16, float>(g, make_coef<float>(params), q, r, st); break;
+    case DP: e = tgv::launch_residual<double, double, double>(g, make_coef<double>(params), params->split, q, r, st); break;
+    case SPDP: e = tgv::launch_residual<double, float, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case SPDP_C64: e = tgv::launch_residual<double, float, double>(g, make_coef<double>(params), params->split, q, r, st); break;
+    case SP_DPC: e = tgv::launch_residual<float, float, double>(g, make_coef<double>(params), params->split, q, r, st); break;
+    case SP: e = tgv::launch_residual<float, float, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case HPSP: e = tgv::launch_residual<float, f16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case HPSP_BF16: e = tgv::launch_residual<float, bf16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case HP: e = tgv::launch_residual<f16, f16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
     default: break;
   }
   return hip_status(e, "ns_residual");
@@ -214,7 +229,7 @@ int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int s
   Form f;
   int rc = check_params(params, &g);
   if (rc) return rc;
-  if ((rc = check_prec(prec, &f))) return rc;
+  if ((rc = check_prec(prec, &f)) || (rc = check_split(params, f))) return rc;
   if (stage < 0 || stage > 2) return fail(NS_ERR_ARG, "stage must be 0, 1 or 2");
   if (!std::isfinite(dt)) return fail(NS_ERR_ARG, "dt must be finite");
   if ((rc = check_ptr(q_in, "q_in")) || (rc = check_ptr(q_out, "q_out")) || (rc = check_ptr(qt, "qt"))) return rc;
@@ -225,35 +240,35 @@ int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int s
   using tgv::f16;
   switch (f) {
     case DP:
-      e = tgv::launch_residual_rk<double, double, double, double, double>(g, make_coef<double>(params), stage, dt,
+      e = tgv::launch_residual_rk<double, double, double, double, double>(g, make_coef<double>(params), params->split, stage, dt,
                                                                           q_in, q_out, qt, st);
       break;
     case SPDP:
-      e = tgv::launch_residual_rk<double, double, float, float, double>(g, make_coef<float>(params), stage, dt, q_in,
+      e = tgv::launch_residual_rk<double, double, float, float, double>(g, make_coef<float>(params), params->split, stage, dt, q_in,
                                                                         q_out, qt, st);
       break;
     case SPDP_C64:
-      e = tgv::launch_residual_rk<double, double, float, double, double>(g, make_coef<double>(params), stage, dt,
+      e = tgv::launch_residual_rk<double, double, float, double, double>(g, make_coef<double>(params), params->split, stage, dt,
                                                                          q_in, q_out, qt, st);
       break;
     case SP_DPC:
-      e = tgv::launch_residual_rk<float, float, float, double, double>(g, make_coef<double>(params), stage, dt, q_in,
+      e = tgv::launch_residual_rk<float, float, float, double, double>(g, make_coef<double>(params), params->split, stage, dt, q_in,
                                                                        q_out, qt, st);
       break;
     case SP:
-      e = tgv::launch_residual_rk<float, float, float, float, float>(g, make_coef<float>(params), stage, dt, q_in,
+      e = tgv::launch_residual_rk<float, float, float, float, float>(g, make_coef<float>(params), params->split, stage, dt, q_in,
                                                                      q_out, qt, st);
       break;
     case HPSP:
-      e = tgv::launch_residual_rk<float, float, f16, float, float>(g, make_coef<float>(params), stage, dt, q_in, q_out,
+      e = tgv::launch_residual_rk<float, float, f16, float, float>(g, make_coef<float>(params), params->split, stage, dt, q_in, q_out,
                                                                    qt, st);
       break;
     case HPSP_BF16:
-      e = tgv::launch_residual_rk<float, float, bf16, float, float>(g, make_coef<float>(params), stage, dt, q_in,
+      e = tgv::launch_residual_rk<float, float, bf16, float, float>(g, make_coef<float>(params), params->split, stage, dt, q_in,
                                                                     q_out, qt, st);
       break;
     case HP:
-      e = tgv::launch_residual_rk<f16, f16, f16, float, float>(g, make_coef<float>(params), stage, dt, q_in, q_out, qt,
+      e = tgv::launch_residual_rk<f16, f16, f16, float, float>(g, make_coef<float>(params), params->split, stage, dt, q_in, q_out, qt,
                                                                st);
       break;
     default: break;
@@ -323,6 +338,7 @@ int ns_residual_adjoint(const ns_params_t* params, const ns_prec_t* prec, const 
   bool f64;
   int rc = check_params(params, &g);
   if (rc) return rc;
+  if ((rc = check_adjoint_split(params))) return rc;
   if ((rc = check_adjoint_prec(prec, &f64))) return rc;
   if ((rc = check_ptr(q, "q")) || (rc = check_ptr(r_bar, "r_bar")) || (rc = check_ptr(q_bar, "q_bar")) ||
       (rc = check_ptr(workspace, "workspace")))

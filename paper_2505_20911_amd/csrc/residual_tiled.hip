@@ -112,6 +112,8 @@ struct LdsNb {
     const int o = (s < 2) ? (s - 2) : (s - 1);
     return lds[f * NPL + own + o * STRIDE];
   }
+  // 1/rho at the neighbour (only the non-Blaisdell split forms need it)
+  __device__ __forceinline__ Tc ir(int s) const { return recip((*this)(F_RHO, s)); }
 };
 
 // The 10 fields of one z-window slot, re-derived from (rho, m, rho E, 1/rho)
@@ -132,13 +134,93 @@ struct WinNb {
   __device__ __forceinline__ Tc operator()(int f, int s) const {
     return derived(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
   }
+  __device__ __forceinline__ Tc ir(int s) const { return (s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D])[W_IR]; }
 };
+
+// The split forms of the convective term D_d(rho u_d phi), phi = (1, u_a, E/rho)
+// for q = rho phi = (rho, m_a, rho E) (Sec. 2.3.1; compared in the inviscid
+// limit in Sec. 4.2).  Blaisdell is the grouped, flux-merged code path in
+// direction_terms; these are the other forms, built from the seven terms
+//   t_div  = D(q u_d)     t_uDq = u_d D(q)     t_qDu  = q D(u_d)
+//   t_phDm = phi D(m_d)   t_mDph = m_d D(phi)  t_rDuf = rho D(u_d phi)
+//   t_ufDr = u_d phi D(rho)
+// combined as: divergence t_div; Feiereisen (t_div + t_phDm + t_mDph)/2;
+// Jameson (t_div + t_rDuf + t_ufDr)/2; Kennedy-Gruber-Pirozzoli the sum of all
+// seven / 4.  The pressure terms stay in divergence form.
+enum { SPLIT_BLAISDELL = 0, SPLIT_DIVERGENCE = 1, SPLIT_FEIEREISEN = 2, SPLIT_JAMESON = 3, SPLIT_KGP = 4 };
+
+template <class Tc, int d, int SPLIT, class Nb>
+__device__ __forceinline__ void split_convection(const Nb& nb, const Tc* c0, Tc ir0, const Coef<Tc>& c,
+                                                 Tc (&R)[5]) {
+  const Tc sc1 = c.c1[d];
+  Tc ud[4], rh[4], md[4], pn[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    ud[s] = nb(F_U + d, s);
+    rh[s] = nb(F_RHO, s);
+    md[s] = nb(F_M + d, s);
+    pn[s] = nb(F_P, s);
+  }
+  const Tc u0 = c0[F_U + d], r0 = c0[F_RHO], m0 = c0[F_M + d];
+  const Tc Dud = S1(ud[0], ud[1], ud[2], ud[3]);
+  const Tc Drho = S1(rh[0], rh[1], rh[2], rh[3]);
+  const Tc Dmd = S1(md[0], md[1], md[2], md[3]);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    Tc qn[4], ph[4], q0, ph0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (f == 0) {
+        qn[s] = rh[s];
+        ph[s] = Tc(1);
+      } else if (f < 4) {
+        qn[s] = nb(F_M + f - 1, s);
+        ph[s] = nb(F_U + f - 1, s);
+      } else {
+        qn[s] = nb(F_E, s);
+        ph[s] = qn[s] * nb.ir(s);
+      }
+    }
+    if (f == 0) {
+      q0 = r0;
+      ph0 = Tc(1);
+    } else if (f < 4) {
+      q0 = c0[F_M + f - 1];
+      ph0 = c0[F_U + f - 1];
+    } else {
+      q0 = c0[F_E];
+      ph0 = c0[F_E] * ir0;
+    }
+    const Tc t_div = S1(qn[0] * ud[0], qn[1] * ud[1], qn[2] * ud[2], qn[3] * ud[3]);
+    Tc cv;
+    if constexpr (SPLIT == SPLIT_DIVERGENCE) {
+      cv = t_div;
+    } else if constexpr (SPLIT == SPLIT_FEIEREISEN) {
+      const Tc t_phDm = ph0 * Dmd, t_mDph = m0 * S1(ph[0], ph[1], ph[2], ph[3]);
+      cv = Tc(0.5) * (t_div + t_phDm + t_mDph);
+    } else if constexpr (SPLIT == SPLIT_JAMESON) {
+      const Tc t_rDuf = r0 * S1(ud[0] * ph[0], ud[1] * ph[1], ud[2] * ph[2], ud[3] * ph[3]);
+      const Tc t_ufDr = u0 * ph0 * Drho;
+      cv = Tc(0.5) * (t_div + t_rDuf + t_ufDr);
+    } else {
+      const Tc t_uDq = u0 * S1(qn[0], qn[1], qn[2], qn[3]);
+      const Tc t_qDu = q0 * Dud;
+      const Tc t_phDm = ph0 * Dmd, t_mDph = m0 * S1(ph[0], ph[1], ph[2], ph[3]);
+      const Tc t_rDuf = r0 * S1(ud[0] * ph[0], ud[1] * ph[1], ud[2] * ph[2], ud[3] * ph[3]);
+      const Tc t_ufDr = u0 * ph0 * Drho;
+      cv = Tc(0.25) * (t_div + t_rDuf + t_uDq + t_phDm + t_mDph + t_qDu + t_ufDr);
+    }
+    R[f] -= sc1 * cv;
+  }
+  R[1 + d] -= sc1 * S1(pn[0], pn[1], pn[2], pn[3]);
+  R[4] -= sc1 * S1(pn[0] * ud[0], pn[1] * ud[1], pn[2] * ud[2], pn[3] * ud[3]);
+}
 
 // Convective + pressure + linear viscous terms of direction d at one point:
 // adds into R and writes the three gradients D_d u_a.  Neighbour values are
 // consumed one field at a time to keep few of them live.
-template <class Tc, int d, class Nb>
-__device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, const Coef<Tc>& c, Tc (&R)[5],
+template <class Tc, int d, int SPLIT, class Nb>
+__device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, Tc ir0, const Coef<Tc>& c, Tc (&R)[5],
                                                 Tc (&G)[3]) {
   const Tc sc1 = c.c1[d];
   const Tc h = Tc(0.5);
@@ -149,6 +231,9 @@ __device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, cons
     pn[s] = nb(F_P, s);
   }
   const Tc Sud = S1(ud[0], ud[1], ud[2], ud[3]);
+  if constexpr (SPLIT != SPLIT_BLAISDELL) {
+    split_convection<Tc, d, SPLIT>(nb, c0, ir0, c, R);
+  } else {
   const Tc hu = h * c0[F_U + d];  // 1/2 u_d at the centre
   const Tc hS = h * Sud;
   // density: flux 1/2 m_d (m_d is read with the momentum below)
@@ -176,6 +261,7 @@ __device__ __forceinline__ void direction_terms(const Nb& nb, const Tc* c0, cons
       F[s] = (h * e[s] + pn[s]) * ud[s];
     }
     R[4] -= sc1 * (S1(F[0], F[1], F[2], F[3]) + hu * S1(e[0], e[1], e[2], e[3]) + c0[F_E] * hS);
+  }
   }
   if (c.viscous) {
     // V_{m_a} gets (1/Re) D2_d u_a, plus (1/Re)(1/3) D2_a u_a for a == d;
@@ -212,7 +298,7 @@ struct RkArgs {
 };
 
 // One z-step with the newest plane in window slot PH.
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int PH>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int PH>
 __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, Ctx<Tc>& cx,
                                       QRing<Tq>& qr,
                                       Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k, Tc (&nxt)[LOADS][5],
@@ -276,8 +362,8 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   Tc R[5] = {0, 0, 0, 0, 0};
   {
     Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
-    direction_terms<Tc, 0>(LdsNb<Tc, 1>{lds, own}, c0, c, R, Gx);
-    direction_terms<Tc, 1>(LdsNb<Tc, HX>{lds, own}, c0, c, R, Gy);
+    direction_terms<Tc, 0, SPLIT>(LdsNb<Tc, 1>{lds, own}, c0, cx.W[PH][W_IR], c, R, Gx);
+    direction_terms<Tc, 1, SPLIT>(LdsNb<Tc, HX>{lds, own}, c0, cx.W[PH][W_IR], c, R, Gy);
     cx.A[PH][0] = Gx[2];
     cx.A[PH][1] = Gy[2];
     cx.A[PH][2] = Gx[0] + Gy[1];
@@ -332,7 +418,7 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
     Tc ck[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) ck[f] = derived(cx.W[K0], f, c);
-    direction_terms<Tc, 2>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W, c}, ck, c, Rz, Gz);
+    direction_terms<Tc, 2, SPLIT>(WinNb<Tc, KM2, KM1, KP1, KP2>{cx.W, c}, ck, cx.W[K0][W_IR], c, Rz, Gz);
     if (c.viscous) {
       const Tc* u0 = ck + F_U;
       // z-mixed: X_x += D_z(w_x), X_y += D_z(w_y), X_z += D_z(u_x + v_y)
@@ -380,7 +466,7 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   __syncthreads();
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
                                                      int tiles_y, int kz, int remap) {
   __shared__ Tc lds[NF * NPL];
@@ -443,21 +529,21 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   // plane p = p_first + t sits in RI slot t % 3; the plane emitted with it,
   // p - 2, in slot (t - 2) % 3 = (t + 1) % 3.
   for (int p = p_first, t = 0; p <= p_last; p += 5, t += 5) {
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 0>(K, rk, cx, qr, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 0>(K, rk, cx, qr, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
     if (p + 1 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 1>(K, rk, cx, qr, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 1>(K, rk, cx, qr, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
     if (p + 2 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 2>(K, rk, cx, qr, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 2>(K, rk, cx, qr, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
     if (p + 3 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 3>(K, rk, cx, qr, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 3>(K, rk, cx, qr, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
     if (p + 4 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, 4>(K, rk, cx, qr, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 4>(K, rk, cx, qr, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
   }
 }
 
 }  // namespace
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
                         hipStream_t st) {
   const int tiles_x = (g.nx + TX - 1) / TX;
@@ -470,29 +556,53 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
-  hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED>), dim3((unsigned)nb), dim3(NT), 0, st, K, rk,
+  hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K, rk,
                      tiles_x, tiles_y, kz, remap);
   return hipGetLastError();
 }
 
+// The non-Blaisdell split forms are instantiated for the FP64 and the
+// half-single forms only (the pair the paper compares them in).
 template <class Tq, class Tr, class Tc>
-hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, const void* q, void* r, hipStream_t st) {
+constexpr bool kAllSplits = (std::is_same<Tq, double>::value && std::is_same<Tr, double>::value &&
+                             std::is_same<Tc, double>::value) ||
+                            (std::is_same<Tq, float>::value && std::is_same<Tr, f16>::value &&
+                             std::is_same<Tc, float>::value);
+
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED>
+hipError_t launch_split(int split, const Grid& g, const Coef<Tc>& c, const void* q, void* r,
+                        const RkArgs<Tq, Tqt, Ta>& rk, hipStream_t st) {
+  if (split == SPLIT_BLAISDELL) return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_BLAISDELL>(g, c, q, r, rk, st);
+  if constexpr (kAllSplits<Tq, Tr, Tc>) {
+    switch (split) {
+      case SPLIT_DIVERGENCE: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_DIVERGENCE>(g, c, q, r, rk, st);
+      case SPLIT_FEIEREISEN: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_FEIEREISEN>(g, c, q, r, rk, st);
+      case SPLIT_JAMESON: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_JAMESON>(g, c, q, r, rk, st);
+      case SPLIT_KGP: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_KGP>(g, c, q, r, rk, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class Tq, class Tr, class Tc>
+hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, int split, const void* q, void* r, hipStream_t st) {
   const RkArgs<Tq, Tq, Tc> none{nullptr, nullptr, Tc(0), Tc(0), Tc(0), 1};
-  return launch_tiled<Tq, Tr, Tc, Tq, Tc, false>(g, c, q, r, none, st);
+  return launch_split<Tq, Tr, Tc, Tq, Tc, false>(split, g, c, q, r, none, st);
 }
 
 template <class Tq, class Tqt, class Tr, class Tc, class Ta>
-hipError_t launch_residual_rk(const Grid& g, const Coef<Tc>& c, int stage, double dt, const void* q_in, void* q_out,
-                              void* qt, hipStream_t st) {
+hipError_t launch_residual_rk(const Grid& g, const Coef<Tc>& c, int split, int stage, double dt, const void* q_in,
+                              void* q_out, void* qt, hipStream_t st) {
   static const double kA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
   static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
   const RkArgs<Tq, Tqt, Ta> rk{static_cast<Tq*>(q_out), static_cast<Tqt*>(qt), (Ta)kA[stage], (Ta)kB[stage],
                                (Ta)dt, stage == 0 ? 1 : 0};
-  return launch_tiled<Tq, Tr, Tc, Tqt, Ta, true>(g, c, q_in, nullptr, rk, st);
+  return launch_split<Tq, Tr, Tc, Tqt, Ta, true>(split, g, c, q_in, nullptr, rk, st);
 }
 
 #define TGV_INST_RES(Tq, Tr, Tc) \
-  template hipError_t launch_residual<Tq, Tr, Tc>(const Grid&, const Coef<Tc>&, const void*, void*, hipStream_t);
+  template hipError_t launch_residual<Tq, Tr, Tc>(const Grid&, const Coef<Tc>&, int, const void*, void*, hipStream_t);
 TGV_INST_RES(double, double, double)
 TGV_INST_RES(double, float, float)
 TGV_INST_RES(double, float, double)
@@ -503,7 +613,7 @@ TGV_INST_RES(float, bf16, float)
 TGV_INST_RES(f16, f16, float)
 
 #define TGV_INST_RRK(Tq, Tqt, Tr, Tc, Ta)                                                                     \
-  template hipError_t launch_residual_rk<Tq, Tqt, Tr, Tc, Ta>(const Grid&, const Coef<Tc>&, int, double,     \
+  template hipError_t launch_residual_rk<Tq, Tqt, Tr, Tc, Ta>(const Grid&, const Coef<Tc>&, int, int, double,\
                                                               const void*, void*, void*, hipStream_t);
 TGV_INST_RRK(double, double, double, double, double)
 TGV_INST_RRK(double, double, float, float, double)

@@ -13,11 +13,11 @@ hipError_t launch_init(const Grid& g, const double L[3], double gamma, double ma
                        hipStream_t st);
 
 template <class Tq, class Tr, class Tc>
-hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, const void* q, void* r, hipStream_t st);
+hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, int split, const void* q, void* r, hipStream_t st);
 
 template <class Tq, class Tqt, class Tr, class Tc, class Ta>
-hipError_t launch_residual_rk(const Grid& g, const Coef<Tc>& c, int stage, double dt, const void* q_in, void* q_out,
-                              void* qt, hipStream_t st);
+hipError_t launch_residual_rk(const Grid& g, const Coef<Tc>& c, int split, int stage, double dt, const void* q_in,
+                              void* q_out, void* qt, hipStream_t st);
 
 template <class Tq, class Tqt, class Tr, class Ta>
 hipError_t launch_rk_stage(const Grid& g, int stage, double dt, void* q, void* qt, const void* r,

@@ -30,7 +30,7 @@ class TgvError(RuntimeError):
 class NsParams(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("L", ctypes.c_double * 3), ("gamma", ctypes.c_double),
                 ("mach", ctypes.c_double), ("reynolds", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("viscous", ctypes.c_int32)]
+                ("viscous", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class NsPrec(ctypes.Structure):
@@ -80,9 +80,14 @@ def load():
     return _lib
 
 
+# Split forms of the convective term (ns_split_t).
+SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4}
+
+
 @dataclass(frozen=True)
 class Params:
-    """Grid and physics (paper Sec. 4.1).  n = (nx, ny, nz)."""
+    """Grid and physics (paper Sec. 4.1).  n = (nx, ny, nz); split selects the
+    convective split form (SPLIT_FORMS)."""
     n: tuple = (32, 32, 32)
     L: tuple = (2 * 3.141592653589793,) * 3
     gamma: float = 1.4
@@ -90,6 +95,7 @@ class Params:
     reynolds: float = 1600.0
     prandtl: float = 0.71
     viscous: int = 1
+    split: int = 0
 
     def c(self) -> NsParams:
         p = NsParams()
@@ -99,6 +105,7 @@ class Params:
         p.gamma, p.mach, p.reynolds, p.prandtl = (float(self.gamma), float(self.mach),
                                                   float(self.reynolds), float(self.prandtl))
         p.viscous = int(self.viscous)
+        p.split = int(self.split)
         return p
 
     @property

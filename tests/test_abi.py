@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert tgv.tgv_abi_version() == 1
+    assert tgv.tgv_abi_version() == 2
 
 
 def _call_residual(params, prec, q=0x1000, r=0x2000):
@@ -102,3 +102,24 @@ def test_python_binding_refuses_host_tensors():
     q = torch.zeros(p.shape, dtype=torch.float64)
     with pytest.raises(ValueError, match="GPU tensor"):
         tgv.ns_residual(p, tgv.PRESETS["DP"], q, q.clone())
+
+
+def test_split_form_validation():
+    """Split forms other than Blaisdell exist for the DP and HPSP forms only;
+    the adjoint rejects them; out-of-range values are rejected -- all before
+    any HIP call (host validation, runs without a GPU)."""
+    lib = tgv.load()
+    dummy = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(4)]
+    p_sp = tgv.Params(n=(8, 8, 8), split=tgv.SPLIT_FORMS["kgp"])
+    for form in ("SP", "SPDP", "HP"):
+        rc = lib.ns_residual(ctypes.byref(p_sp.c()), ctypes.byref(tgv.PRESETS[form].c()), dummy[0], dummy[1], None)
+        assert rc == NS_ERR_ARG, form
+        rc = lib.ns_residual_rk_stage(ctypes.byref(p_sp.c()), ctypes.byref(tgv.PRESETS[form].c()), 0, 1e-3,
+                                      dummy[0], dummy[1], dummy[2], None)
+        assert rc == NS_ERR_ARG, form
+    rc = lib.ns_residual_adjoint(ctypes.byref(p_sp.c()), ctypes.byref(tgv.PRESETS["DP"].c()), dummy[0], dummy[1],
+                                 dummy[2], dummy[3], None)
+    assert rc == NS_ERR_ARG and b"Blaisdell" in lib.ns_last_error()
+    bad = tgv.Params(n=(8, 8, 8), split=7)
+    rc = lib.ns_residual(ctypes.byref(bad.c()), ctypes.byref(tgv.PRESETS["DP"].c()), dummy[0], dummy[1], None)
+    assert rc == NS_ERR_ARG and b"split" in lib.ns_last_error()

@@ -10,7 +10,7 @@ def oracle_params(p):
     """oracle.Params with the same grid and physics as a binding Params."""
     import oracle as O
     return O.Params(n=tuple(p.n), L=tuple(p.L), gamma=p.gamma, mach=p.mach, re=p.reynolds, pr=p.prandtl,
-                    viscous=p.viscous)
+                    viscous=p.viscous, split=p.split)
 
 
 def term_scale(n, L, gamma, q):
