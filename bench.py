@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--paths", default="fused,split", help="fused and/or split residual + stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint kernels and gradient timing")
+    ap.add_argument("--no-splits", action="store_true", help="skip the timing of the other split forms")
     ap.add_argument("--cpu-n", type=int, default=256, help="grid of the oracle sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 launches), to calibrate the "
@@ -235,6 +236,48 @@ def adjoint_leg(n, form="DP", launches=5):
     return out
 
 
+def split_leg(n, steps=5):
+    """Fused-stage duration and throughput of the other split forms of the
+    convective term (divergence, Feiereisen, Jameson, KGP) in the DP and HPSP
+    forms at n^3: 1 warm-up step, then `steps` steps with HIP events around
+    each fused launch."""
+    import torch
+    from paper_2505_20911_amd import tgv
+    from paper_2505_20911_amd.solver import TGVSolver
+    out = {}
+    dt = 3.7e-3 * 32 / n
+    for name, split in tgv.SPLIT_FORMS.items():
+        if split == 0:
+            continue
+        for form in ("DP", "HPSP"):
+            prec = tgv.PRESETS[form]
+            p = tgv.Params(n=(n, n, n), split=split)
+            s = TGVSolver(p, prec)
+            s.init()
+            s.step(dt)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            evs = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                for i in range(3):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    s.stage(i, dt)
+                    b.record(stream)
+                    evs.append((a, b, i))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            bq, bqt = nbytes(prec.q), nbytes(prec.qt)
+            ms = sum(a.elapsed_time(b) for a, b, _ in evs) / len(evs)
+            byts = sum(5 * p.N * (2 * bq + (bqt if i == 0 else 2 * bqt)) for _, _, i in evs) / len(evs)
+            out[f"{name}/{form}"] = {"mpt_stage_per_s": p.N * 3 * steps / (wall * 1e6), "fused_avg_ms": ms,
+                                     "fused_gbs": byts / (ms * 1e-3) / 1e9}
+            del s
+            torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n):
     """One RK3 step (three residual + stage pairs) of the FP64 oracle on an
     n^3 Taylor-Green grid: same per-point work as the GPU workload, sized to
@@ -317,6 +360,11 @@ def main():
               + "; gradient " + ", ".join(f"{k} {v['wall_s']:.2f} s" for k, v in
                                           line["adjoint"]["gradient_128_400steps_20slots"].items()),
               file=sys.stderr, flush=True)
+    if not args.no_splits:
+        print(f"[bench] split forms at {n}^3 (DP, HPSP)", file=sys.stderr, flush=True)
+        line["split_forms"] = split_leg(n)
+        print("[bench] split forms: " + ", ".join(f"{k} {v['fused_avg_ms']:.2f} ms" for k, v in
+                                                  line["split_forms"].items()), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on {args.cpu_n}^3", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_n)

@@ -322,3 +322,56 @@ def test_fused_stage_full_size_sampled(n):
     tol_q = 4 * u * (np.abs(q_s) + np.abs(B * ref_qt)) + B * tol_qt
     assert np.all(np.abs(got_qt - ref_qt) <= tol_qt), np.max(np.abs(got_qt - ref_qt) / tol_qt)
     assert np.all(np.abs(got_q - ref_q) <= tol_q), np.max(np.abs(got_q - ref_q) / tol_q)
+
+
+@pytest.mark.parametrize("form", ["SPDP", "SP", "HPSP", "HP"])
+def test_fused_stage_full_size_sampled_reduced_forms(form):
+    """The benchmark's launch for the reduced forms at 512^3: one fused stage
+    (stage 2 of 3) on Q rounded to its storage type, compared at 2000 sampled
+    points with the oracle's pointwise residual of the same (widened) Q, within
+    the rounding bound of the arithmetic, R storage and register/state
+    storage types."""
+    say("fused full size sampled", form)
+    n = 512
+    prec = tgv.PRESETS[form]
+    p = tgv.Params(n=(n, n, n))
+    po = oracle_params(p)
+    q64 = O.init(po)
+    q64[1:4] *= 1.0 + 0.01 * np.cos(np.arange(n))[None, None, None, :]
+    qs = rounded(q64, prec.q)
+    del q64
+    rng = np.random.default_rng(n + 2)
+    idx = np.unique(np.concatenate([rng.choice(p.N, 2000, replace=False),
+                                    [0, n - 1, n * n - 1, p.N - 1]])).astype(np.int64)
+    qw = widened(qs)
+    R = O.residual_at(po, qw, idx)
+    scale = term_scale(p.n, p.L, p.gamma, qw)
+    q_s = qw.reshape(5, -1)[:, idx].T.copy()
+    del qw
+    qt_s = 0.5 * q_s  # the register is Q / 2 (exact in every storage type here)
+    q = qs.to(DEV)
+    del qs
+    qt = (q * 0.5).to(prec.qt)
+    q_out = torch.empty_like(q)
+    stage, dt = 1, 2.3125e-4
+    tgv.ns_residual_rk_stage(p, prec, stage, dt, q, q_out, qt)
+    ti = torch.from_numpy(idx).to(DEV)
+    got_qt = widened(qt.reshape(5, -1)[:, ti].T)
+    got_q = widened(q_out.reshape(5, -1)[:, ti].T)
+    del q, qt, q_out
+    torch.cuda.empty_cache()
+    A, B = O.RK_A[stage], O.RK_B[stage]
+    uc, ur = UNIT_ROUNDOFF[prec.compute], UNIT_ROUNDOFF[prec.r]
+    ua = 2.0 ** -53 if torch.float64 in (prec.q, prec.compute) else 2.0 ** -24
+    ut, uq = UNIT_ROUNDOFF[prec.qt], UNIT_ROUNDOFF[prec.q]
+    tol_R = 64 * uc * scale[None, :] + 2 * ur * np.abs(R)
+    ref_qt = A * qt_s + dt * R
+    ref_q = q_s + B * ref_qt
+    # half the smallest FP16 subnormal spacing: values near zero round on an absolute grid
+    tiny_t = 2.0 ** -25 if prec.qt == torch.float16 else 0.0
+    tiny_q = 2.0 ** -25 if prec.q == torch.float16 else 0.0
+    tol_qt = dt * tol_R + 2 * ua * (np.abs(A * qt_s) + dt * np.abs(R)) + ut * np.abs(ref_qt) + tiny_t
+    tol_q = B * tol_qt + 2 * ua * (np.abs(q_s) + abs(B) * np.abs(ref_qt)) + uq * np.abs(ref_q) + tiny_q
+    say("  max err / tol", np.max(np.abs(got_qt - ref_qt) / tol_qt), np.max(np.abs(got_q - ref_q) / tol_q))
+    assert np.all(np.abs(got_qt - ref_qt) <= tol_qt)
+    assert np.all(np.abs(got_q - ref_q) <= tol_q)
