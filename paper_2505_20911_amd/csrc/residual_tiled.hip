@@ -441,7 +441,7 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
       const long long id = (long long)k * g.plane + col_off;
       if (!FUSED) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) K.r[f * g.N + id] = store_as<Tr>(Rz[f]);
+        for (int f = 0; f < 5; ++f) stream_store(&K.r[f * g.N + id], store_as<Tr>(Rz[f]));
       } else {
         // Q~ <- A Q~ + dt R ; Q_out <- Q_in + B Q~, with R rounded to its
         // storage type as a stored residual would be.  Q_in at this point is
@@ -451,13 +451,13 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
         for (int f = 0; f < 5; ++f) {
           const Ta rr = load_as<Ta>(store_as<Tr>(Rz[f]));
           const Tqt ts = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f]), rr));
-          rk.qt[f * g.N + id] = ts;
+          stream_store(&rk.qt[f * g.N + id], ts);
           Ta qin;
           if constexpr (kQinFromWindow)
             qin = ck[f];
           else
             qin = load_as<Ta>(qr.v[K0][f]);
-          rk.q_out[f * g.N + id] = store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts)));
+          stream_store(&rk.q_out[f * g.N + id], store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts))));
         }
       }
     }

@@ -109,6 +109,16 @@ template <>
 __device__ __forceinline__ float load_as<float, bf16>(bf16 v) { return Conv<bf16>::load_f32(v); }
 
 // Store an arithmetic value into storage type T (RNE, correctly rounded).
+// Store that streams past the caches (the nontemporal hint on a vector
+// store): for outputs written once and not read again by the same kernel.
+template <class T>
+__device__ __forceinline__ void stream_store(T* p, T v) {
+  if constexpr (std::is_arithmetic<T>::value || std::is_same<T, _Float16>::value)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 template <class T, class Tc>
 __device__ __forceinline__ T store_as(Tc x) {
   return Conv<T>::from(x);
