@@ -45,12 +45,6 @@ __device__ __forceinline__ long long nb(const Grid& g, long long id, const int i
   return id + (long long)(t - ijk[2]) * g.plane;
 }
 
-__device__ __forceinline__ void coords(const Grid& g, long long id, int ijk[3]) {
-  ijk[0] = (int)(id % g.nx);
-  ijk[1] = (int)((id / g.nx) % g.ny);
-  ijk[2] = (int)(id / g.plane);
-}
-
 // Gather kernels walk columns: a block owns a CX x CY tile of (x, y) columns
 // and a chunk of kz planes, x fastest, and each thread loops over its column's
 // planes, so the z-neighbour rows it reads were read by the same block a step

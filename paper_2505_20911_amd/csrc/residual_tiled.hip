@@ -14,15 +14,20 @@
 //      made of in-plane gradients only) and parks that partial R in a
 //      thread-private LDS ring; it keeps three gradient combinations in
 //      registers: D_x w, D_y w and D_x u + D_y v;
-//   3. emits R for plane p - 2: its z-derivative terms come from a 5-plane
-//      register window of the 10 fields; the z-mixed derivatives of the
-//      viscous term are z-differences of the three stored combinations, which
-//      are also all that the remaining (in-plane x z) part of tau : grad u needs.
+//   3. emits R (or, fused, the RK stage) for plane p - 2: its z-derivative
+//      terms come from a 5-plane register window of (rho, m, rho E, 1/rho),
+//      from which u, v, w, p and T are re-derived where needed; the z-mixed
+//      derivatives of the viscous term are z-differences of the three stored
+//      combinations, which are also all that the remaining (in-plane x z) part
+//      of tau : grad u needs.
 // The z loop is unrolled by the window length (5) so that the window rotates
 // by renaming, not by register moves.  The next plane's loads are issued
-// before the current plane's arithmetic.  Tiles are ordered so that
-// y-neighbours (which share halo rows) run on the same XCD, whose L2 then
-// serves the halo re-reads.
+// before the current plane's arithmetic.  Tiles are ordered x fastest in
+// contiguous runs per XCD, so the blocks resident on one XCD cover whole rows
+// of tiles and their halo re-reads hit that XCD's L2.  Outputs are streamed
+// with the nontemporal hint.  The other split forms of the convective term
+// (Sec. 2.3.1, compared in Sec. 4.2) replace the grouped fluxes by a generic
+// seven-term combination (split_convection).
 //
 // Every 4th-order stencil is taken as S(f) = 8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2})
 // (times 1/(12 h)) and S2(f) = 16 (f_{+1} + f_{-1} - 2 f_0) - (f_{+2} + f_{-2} - 2 f_0)
@@ -42,10 +47,10 @@ namespace tgv {
 namespace {
 
 constexpr int TX = 64, TY = 8, NT = TX * TY;
-// Waves per SIMD the register allocation must allow: FP64 arithmetic is
-// latency-bound at one wave per SIMD and gains from a second one even at the
-// price of a few spilled registers; the FP32 forms are VALU-bound and fit two
-// waves anyway (measured at 512^3).
+// Waves per SIMD the register allocation must allow: the FP64-arithmetic
+// instances are held to 2 (256 VGPRs, a few spilled in the fused kernel; one
+// wave with no spills measured the same within 2 % at 512^3); the FP32
+// instances fit two waves without a bound.
 template <class Tc>
 constexpr int kWavesPerEU = sizeof(Tc) == 8 ? 2 : 1;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
