@@ -82,6 +82,28 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
+def copy_ceiling(gib=4, reps=5):
+    """Achieved bandwidth of a plain device-to-device copy (torch copy_ of
+    `gib` GiB, read + write bytes over the event-timed duration): the
+    practical streaming ceiling the stencil kernels are compared with."""
+    import torch
+    n = gib * (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def nbytes(dtype):
     import torch
     return torch.empty((), dtype=dtype).element_size()
@@ -321,6 +343,8 @@ def main():
             r = results[key]
             ks = ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['gbs']:.0f} GB/s" for k, v in r["kernels"].items())
             print(f"[bench] {key}: {r['mpt_stage_per_s']:.0f} Mpt.stage/s ({ks})", file=sys.stderr, flush=True)
+    copy_gbs = copy_ceiling()
+    print(f"[bench] device copy ceiling {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     head_key = "DP" if "DP" in results else next(iter(results))
     head = results[head_key]
     for key, r in results.items():
@@ -349,7 +373,8 @@ def main():
                      "frac": hk["gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(("ns_residual_rk_stage" if kname == "fused" else "ns_residual")
                                                  + f"/{head_key}/{n}"),
-                     "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"]},
+                     "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"],
+                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": hk["gbs"] / copy_gbs},
         "forms": results,
     }
     if not args.no_adjoint:

@@ -58,15 +58,20 @@ constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thre
 constexpr int NF = 10;
 enum { F_RHO = 0, F_M = 1, F_E = 4, F_U = 5, F_P = 8, F_T = 9 };
 
-// Fields kept per plane in the z-window: the conserved variables and 1/rho;
-// u, v, w, p and T are re-derived from them where the z-stencils need them.
-constexpr int NW = 6;
-enum { W_IR = 5 };
+// Fields kept per plane in the z-window: the conserved variables and 1/rho,
+// and for FP32 arithmetic (registers to spare at two waves per SIMD) also u,
+// v, w, p and T; the FP64 instances re-derive those five where the
+// z-stencils need them, exactly as primitives() derives them.
+template <class Tc>
+constexpr bool kFullWindow = sizeof(Tc) < 8;
+template <class Tc>
+constexpr int NW = kFullWindow<Tc> ? 11 : 6;
+enum { W_IR = 5 };  // then u, v, w, p, T at 6..10 in the full window
 
 template <class Tc>
 struct Ctx {
-  // z-window: rho, m1, m2, m3, rho E, 1/rho of this column at the last 5 planes
-  Tc W[5][NW];
+  // z-window of this column at the last 5 planes
+  Tc W[5][NW<Tc>];
   // per plane slot: 0: D_x w, 1: D_y w, 2: D_x u + D_y v
   Tc A[5][3];
 };
@@ -121,11 +126,12 @@ struct LdsNb {
   __device__ __forceinline__ Tc ir(int s) const { return recip((*this)(F_RHO, s)); }
 };
 
-// The 10 fields of one z-window slot, re-derived from (rho, m, rho E, 1/rho)
-// exactly as primitives() derives them.
+// The 10 fields of one z-window slot: stored, or re-derived from
+// (rho, m, rho E, 1/rho) exactly as primitives() derives them.
 template <class Tc>
 __device__ __forceinline__ Tc derived(const Tc* w, int f, const Coef<Tc>& c) {
   if (f < 5) return w[f];
+  if constexpr (kFullWindow<Tc>) return w[f + 1];
   if (f < F_P) return w[f - 4] * w[W_IR];
   const Tc u = w[1] * w[W_IR], v = w[2] * w[W_IR], x = w[3] * w[W_IR];
   const Tc p = c.gm1 * (w[4] - Tc(0.5) * (w[1] * u + w[2] * v + w[3] * x));
@@ -134,7 +140,7 @@ __device__ __forceinline__ Tc derived(const Tc* w, int f, const Coef<Tc>& c) {
 
 template <class Tc, int A, int B, int C, int D>
 struct WinNb {
-  const Tc (&W)[5][NW];
+  const Tc (&W)[5][NW<Tc>];
   const Coef<Tc>& c;
   __device__ __forceinline__ Tc operator()(int f, int s) const {
     return derived(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
@@ -364,6 +370,10 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
 #pragma unroll
   for (int k = 0; k < 5; ++k) cx.W[PH][k] = c0[k];
   cx.W[PH][W_IR] = recip(c0[F_RHO]);
+  if constexpr (kFullWindow<Tc>) {
+#pragma unroll
+    for (int k = F_U; k < NF; ++k) cx.W[PH][k + 1] = c0[k];
+  }
   Tc R[5] = {0, 0, 0, 0, 0};
   {
     Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
