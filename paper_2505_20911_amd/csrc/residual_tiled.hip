@@ -47,12 +47,11 @@ namespace tgv {
 namespace {
 
 constexpr int TX = 64, TY = 8, NT = TX * TY;
-// Waves per SIMD the register allocation must allow: the FP64-arithmetic
-// instances are held to 2 (256 VGPRs, a few spilled in the fused kernel; one
-// wave with no spills measured the same within 2 % at 512^3); the FP32
-// instances fit two waves without a bound.
+// A 512-thread block is two waves on each of the CU's four SIMDs, so every
+// instance has at most 256 VGPRs per lane; the FP64 fused instances spill a
+// few registers at that limit, the FP32 ones fit with room to spare.
 template <class Tc>
-constexpr int kWavesPerEU = sizeof(Tc) == 8 ? 2 : 1;
+constexpr int kWavesPerEU = 2;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
 constexpr int NF = 10;
