@@ -136,7 +136,11 @@ def time_form(form, n, steps, warmup, dt, fused):
     row = 0
     for k in range(steps):
         if k % every == 0:
+            a, b = ev(), ev()
+            a.record(stream)
             s.integrals(hist[row])
+            b.record(stream)
+            k_ev.append((a, b, "integrals", 0))
             row += 1
         for i in range(3):
             if fused:
@@ -165,6 +169,7 @@ def time_form(form, n, steps, warmup, dt, fused):
         "residual": lambda i: 5 * N * (bq + br),
         "rk_stage": lambda i: 5 * N * (br + 2 * bq + (bqt if i == 0 else 2 * bqt)),
         "fused": lambda i: 5 * N * (2 * bq + (bqt if i == 0 else 2 * bqt)),
+        "integrals": lambda i: 5 * N * bq,
     }
     kern = {}
     for a, b, kind, i in k_ev:

@@ -66,7 +66,11 @@ __global__ void __launch_bounds__(kThreads) integrals_pass1(Grid g, Coef<double>
                                                             int kz) {
   __shared__ double vel[2][3][IPL];  // double-buffered velocity plane
   __shared__ double red[4];
-  const int b = blockIdx.x;
+  // contiguous runs of tiles per XCD (hardware block b runs on XCD b % 8),
+  // x fastest, so that neighbouring tiles' halo rows meet in one L2
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
   const int x0 = (b % tiles_x) * IX;
   const int y0 = ((b / tiles_x) % tiles_y) * IY;
   const int z0 = (b / (tiles_x * tiles_y)) * kz;
