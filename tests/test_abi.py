@@ -123,3 +123,28 @@ def test_split_form_validation():
     bad = tgv.Params(n=(8, 8, 8), split=7)
     rc = lib.ns_residual(ctypes.byref(bad.c()), ctypes.byref(tgv.PRESETS["DP"].c()), dummy[0], dummy[1], None)
     assert rc == NS_ERR_ARG and b"split" in lib.ns_last_error()
+
+
+def test_last_error_is_per_thread():
+    """ns_last_error() is thread-local: a failing call on one thread does not
+    overwrite the message another thread is about to read."""
+    import threading
+    lib = tgv.load()
+    msgs = {}
+    gate = threading.Barrier(2)
+
+    def worker(name, n):
+        p = tgv.Params(n=(n, 8, 8))
+        gate.wait()
+        rc = lib.ns_residual(ctypes.byref(p.c()), ctypes.byref(tgv.PRESETS["DP"].c()), ctypes.c_void_p(0x1001),
+                             ctypes.c_void_p(0x2000), None)
+        gate.wait()
+        msgs[name] = (rc, lib.ns_last_error())
+
+    ts = [threading.Thread(target=worker, args=("shape", 3)), threading.Thread(target=worker, args=("align", 8))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert msgs["shape"][0] == NS_ERR_SHAPE and b"n[0]" in msgs["shape"][1]
+    assert msgs["align"][0] == NS_ERR_ALIGN and b"aligned" in msgs["align"][1]

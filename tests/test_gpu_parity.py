@@ -375,3 +375,21 @@ def test_fused_stage_full_size_sampled_reduced_forms(form):
     say("  max err / tol", np.max(np.abs(got_qt - ref_qt) / tol_qt), np.max(np.abs(got_q - ref_q) / tol_q))
     assert np.all(np.abs(got_qt - ref_qt) <= tol_qt)
     assert np.all(np.abs(got_q - ref_q) <= tol_q)
+
+
+def test_solver_on_a_side_stream_matches_default_stream():
+    """Every entry point enqueues on the stream it is given: a run on a
+    non-default stream (no implicit synchronisation with the default one) is
+    bitwise equal to the same run on the default stream."""
+    p = tgv.Params(n=(24, 32, 40))
+    a = TGVSolver(p, tgv.PRESETS["DP"])
+    a.init()
+    ha = a.run(4, 3e-3, every=2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b = TGVSolver(p, tgv.PRESETS["DP"], stream=side.cuda_stream)
+        b.init()
+        hb = b.run(4, 3e-3, every=2)
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a.q, b.q) and torch.equal(ha, hb)
