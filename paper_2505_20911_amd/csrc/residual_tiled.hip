@@ -27,7 +27,8 @@
 // of tiles and their halo re-reads hit that XCD's L2.  Outputs are streamed
 // with the nontemporal hint.  The other split forms of the convective term
 // (Sec. 2.3.1, compared in Sec. 4.2) replace the grouped fluxes by a generic
-// seven-term combination (split_convection).
+// seven-term combination (split_convection).  FP64-arithmetic instances use
+// a warp-specialised variant of the same step (residual_ws, below).
 //
 // Every 4th-order stencil is taken as S(f) = 8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2})
 // (times 1/(12 h)) and S2(f) = 16 (f_{+1} + f_{-1} - 2 f_0) - (f_{+2} + f_{-2} - 2 f_0)
@@ -113,13 +114,13 @@ __device__ __forceinline__ void primitives(const Tc q[5], Tc* out, const Coef<Tc
 
 // Neighbour accessors: field f at offset index s (0..3 = -2, -1, +1, +2)
 // along one direction, from the LDS plane (x, y) or the z-window.
-template <class Tc, int STRIDE>
+template <class Tc, int STRIDE, int PLANE = NPL>
 struct LdsNb {
   const Tc* lds;
   int own;
   __device__ __forceinline__ Tc operator()(int f, int s) const {
     const int o = (s < 2) ? (s - 2) : (s - 1);
-    return lds[f * NPL + own + o * STRIDE];
+    return lds[f * PLANE + own + o * STRIDE];
   }
   // 1/rho at the neighbour (only the non-Blaisdell split forms need it)
   __device__ __forceinline__ Tc ir(int s) const { return recip((*this)(F_RHO, s)); }
@@ -555,13 +556,323 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Warp-specialised variant, used for the FP64-arithmetic instances.  A block
+// of 2 x 256 threads owns a 64 x 4 tile: threads [0, 256) take the in-plane
+// role, threads [256, 512) the z role, one column each, so that each SIMD
+// holds one wave of each kind and the LDS-heavy in-plane phase of one
+// overlaps the FP64 arithmetic of the other.  At step t (plane p = p_first + t):
+//   in-plane: x/y terms of plane p from LDS buffer t % 2 -> partial R into ring
+//             slot t % 4 and the gradient combinations into slot t % 2;
+//   z:        primitives of plane p + 1 into LDS buffer (t + 1) % 2, loads of
+//             plane p + 2, own column of plane p into window slot t % 6, the
+//             combinations of plane p - 1 from the ring, and the emission of
+//             plane p - 3 (z terms, z-mixed terms, store or RK stage).
+// One barrier per step (double-buffered plane).  Measured at 512^3: FP64
+// fused stage 5 % faster than the single-role kernel above; the FP32 forms
+// are faster with the single-role kernel (larger tile, less halo work).
+constexpr int WS_TY = 4, WS_NCOL = TX * WS_TY, WS_NT = 2 * WS_NCOL;
+constexpr int WS_HY = WS_TY + 4, WS_NPL = HX * WS_HY;
+constexpr int WS_LOADS = (WS_NPL + WS_NCOL - 1) / WS_NCOL;
+
+template <class Tc, int A, int B, int C, int D>
+struct WinNb6 {
+  const Tc (&W)[6][NW<Tc>];
+  const Coef<Tc>& c;
+  __device__ __forceinline__ Tc operator()(int f, int s) const {
+    return derived(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
+  }
+  __device__ __forceinline__ Tc ir(int s) const { return (s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D])[W_IR]; }
+};
+
+constexpr int WL = 6;  // z-window length: emission lags the newest plane by 3
+constexpr int RR_SLOTS = 4, RA_SLOTS = 2;
+
+template <class Tc>
+struct ZCtx {
+  Tc W[WL][NW<Tc>];
+  Tc A[WL][3];
+};
+
+template <class Tq>
+struct QRing6 {
+  Tq v[WL][5];
+};
+
+template <class Tc, int SPLIT>
+__device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ring_r, Tc* ring_a, int col) {
+  const int tx = col % TX, ty = col / TX;
+  const int own = (ty + 2) * HX + (tx + 2);
+  Tc c0[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) c0[k] = lds[k * WS_NPL + own];
+  const Tc ir0 = SPLIT != SPLIT_BLAISDELL ? recip(c0[F_RHO]) : Tc(0);
+  Tc R[5] = {0, 0, 0, 0, 0};
+  Tc A3[3];
+  {
+    Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
+    direction_terms<Tc, 0, SPLIT>(LdsNb<Tc, 1, WS_NPL>{lds, own}, c0, ir0, c, R, Gx);
+    direction_terms<Tc, 1, SPLIT>(LdsNb<Tc, HX, WS_NPL>{lds, own}, c0, ir0, c, R, Gy);
+    A3[0] = Gx[2];
+    A3[1] = Gy[2];
+    A3[2] = Gx[0] + Gy[1];
+    if (c.viscous) {
+      const Tc a3 = A3[2];
+      const Tc sq = Gx[0] * Gx[0] + Gx[1] * Gx[1] + Gx[2] * Gx[2] + Gy[0] * Gy[0] + Gy[1] * Gy[1] + Gy[2] * Gy[2];
+      const Tc cr = Gx[0] * Gx[0] + Gy[1] * Gy[1] + Tc(2) * Gy[0] * Gx[1];
+      R[4] += c.ire * (sq + cr - Tc(2.0 / 3.0) * a3 * a3);
+    }
+  }
+  if (c.viscous) {
+    const int offs[4] = {-2, -1, 1, 2};
+    Tc iv[4], iu[4];
+#pragma unroll
+    for (int sy = 0; sy < 4; ++sy) {
+      const int row = own + offs[sy] * HX;
+      iv[sy] = S1(lds[(F_U + 1) * WS_NPL + row - 2], lds[(F_U + 1) * WS_NPL + row - 1], lds[(F_U + 1) * WS_NPL + row + 1],
+                  lds[(F_U + 1) * WS_NPL + row + 2]);
+    }
+#pragma unroll
+    for (int sx = 0; sx < 4; ++sx) {
+      const int cl = own + offs[sx];
+      iu[sx] = S1(lds[F_U * WS_NPL + cl - 2 * HX], lds[F_U * WS_NPL + cl - HX], lds[F_U * WS_NPL + cl + HX],
+                  lds[F_U * WS_NPL + cl + 2 * HX]);
+    }
+    const Tc cxy = c.c1[0] * c.c1[1] * c.ire * Tc(1.0 / 3.0);
+    const Tc mx = cxy * S1(iv[0], iv[1], iv[2], iv[3]);
+    const Tc my = cxy * S1(iu[0], iu[1], iu[2], iu[3]);
+    R[1] += mx;
+    R[2] += my;
+    R[4] += c0[F_U] * mx + c0[F_U + 1] * my;
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) ring_r[f * WS_NCOL + col] = R[f];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ring_a[a * WS_NCOL + col] = A3[a];
+}
+
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int PH>
+__device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, ZCtx<Tc>& zc,
+                                       QRing6<Tq>& qr, const Tc* cur, Tc* next, const Tc* ring_r,
+                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[WS_LOADS][5],
+                                       const long long (&off)[WS_LOADS], int p, int z0, int z1, int p_last,
+                                       bool col_valid, long long col_off, int zt) {
+  constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
+  const Grid& g = K.g;
+  const Coef<Tc>& c = K.c;
+  const int k = p - 3;
+  const bool emit = k >= z0 && k < z1;
+  Tqt qt_k[5] = {Tqt(), Tqt(), Tqt(), Tqt(), Tqt()};
+  if (FUSED && emit && col_valid && !rk.first) {
+    const long long id = (long long)k * g.plane + col_off;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qt_k[f] = rk.qt[f * g.N + id];
+  }
+  // 1. primitives of plane p + 1 into the other buffer; loads of plane p + 2
+  if (p + 1 <= p_last) {
+#pragma unroll
+    for (int l = 0; l < WS_LOADS; ++l) {
+      const int s = zt + l * WS_NCOL;
+      if (s < WS_NPL) {
+        Tc f[NF];
+        primitives(nxt[l], f, c);
+#pragma unroll
+        for (int m = 0; m < NF; ++m) next[m * WS_NPL + s] = f[m];
+      }
+    }
+    if (p + 2 <= p_last) {
+      int z = p + 2;
+      z += (z < 0) ? g.nz : 0;
+      z -= (z >= g.nz) ? g.nz : 0;
+      const long long zo = (long long)z * g.plane;
+#pragma unroll
+      for (int l = 0; l < WS_LOADS; ++l) {
+        const int s = zt + l * WS_NCOL;
+        if (s < WS_NPL) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) nxt[l][f] = load_as<Tc>(K.q[f * g.N + zo + off[l]]);
+        }
+      }
+    }
+  }
+  // 2. own column of plane p into window slot PH
+  if (p <= p_last) {
+    const int tx = zt % TX, ty = zt / TX;
+    const int own = (ty + 2) * HX + (tx + 2);
+    Tc c0[NF];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) c0[m] = cur[m * WS_NPL + own];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) zc.W[PH][m] = c0[m];
+    zc.W[PH][W_IR] = recip(c0[F_RHO]);
+    if constexpr (kFullWindow<Tc>) {
+#pragma unroll
+      for (int m = F_U; m < NF; ++m) zc.W[PH][m + 1] = c0[m];
+    }
+    if (FUSED && !kQinFromWindow && p >= z0 && p < z1 && col_valid) {
+      const long long id = (long long)p * g.plane + col_off;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qr.v[PH][f] = K.q[f * g.N + id];
+    }
+  }
+  // 3. gradient combinations of plane p - 1
+  if (have_prev) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zc.A[(PH + WL - 1) % WL][a] = ring_a_prev[a * WS_NCOL + zt];
+  }
+  // 4. emit plane k = p - 3 (window slots of k - 2 .. k + 2)
+  if (emit) {
+    constexpr int KM2 = (PH + 1) % WL, KM1 = (PH + 2) % WL, K0 = (PH + 3) % WL, KP1 = (PH + 4) % WL,
+                  KP2 = (PH + 5) % WL;
+    Tc Rz[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) Rz[f] = ring_r[f * WS_NCOL + zt];
+    Tc Gz[3] = {0, 0, 0};
+    Tc ck[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) ck[f] = derived(zc.W[K0], f, c);
+    direction_terms<Tc, 2, SPLIT>(WinNb6<Tc, KM2, KM1, KP1, KP2>{zc.W, c}, ck, zc.W[K0][W_IR], c, Rz, Gz);
+    if (c.viscous) {
+      const Tc* u0 = ck + F_U;
+      const Tc cz = c.c1[2] * c.ire * Tc(1.0 / 3.0);
+      const Tc mx = cz * S1(zc.A[KM2][0], zc.A[KM1][0], zc.A[KP1][0], zc.A[KP2][0]);
+      const Tc my = cz * S1(zc.A[KM2][1], zc.A[KM1][1], zc.A[KP1][1], zc.A[KP2][1]);
+      const Tc mz = cz * S1(zc.A[KM2][2], zc.A[KM1][2], zc.A[KP1][2], zc.A[KP2][2]);
+      Rz[1] += mx;
+      Rz[2] += my;
+      Rz[3] += mz;
+      Rz[4] += u0[0] * mx + u0[1] * my + u0[2] * mz;
+      const Tc a1 = zc.A[K0][0], a2 = zc.A[K0][1], a3 = zc.A[K0][2];
+      const Tc sq = Gz[0] * Gz[0] + Gz[1] * Gz[1] + Gz[2] * Gz[2];
+      const Tc cr = Tc(2) * (Gz[0] * a1 + Gz[1] * a2) + Gz[2] * Gz[2];
+      Rz[4] += c.ire * (sq + cr - Tc(2.0 / 3.0) * (Tc(2) * a3 + Gz[2]) * Gz[2]);
+    }
+    if (col_valid) {
+      const long long id = (long long)k * g.plane + col_off;
+      if (!FUSED) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) stream_store(&K.r[f * g.N + id], store_as<Tr>(Rz[f]));
+      } else {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          const Ta rr = load_as<Ta>(store_as<Tr>(Rz[f]));
+          const Tqt ts = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f]), rr));
+          stream_store(&rk.qt[f * g.N + id], ts);
+          Ta qin;
+          if constexpr (kQinFromWindow)
+            qin = ck[f];
+          else
+            qin = load_as<Ta>(qr.v[K0][f]);
+          stream_store(&rk.q_out[f * g.N + id], store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts))));
+        }
+      }
+    }
+  }
+}
+
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
+__global__ void __launch_bounds__(WS_NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
+                                                                      int tiles_x, int tiles_y, int kz, int remap) {
+  __shared__ Tc lds[2][NF * WS_NPL];
+  __shared__ Tc ring_r[RR_SLOTS][5 * WS_NCOL];
+  __shared__ Tc ring_a[RA_SLOTS][3 * WS_NCOL];
+  const Grid& g = K.g;
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nb / 8) + b / 8;
+  const int tx_t = b % tiles_x;
+  const int ty_t = (b / tiles_x) % tiles_y;
+  const int cz = b / (tiles_y * tiles_x);
+  const int x0 = tx_t * TX, y0 = ty_t * WS_TY;
+  const int z0 = cz * kz;
+  const int z1 = min(z0 + kz, g.nz);
+  const bool zrole = threadIdx.x >= WS_NCOL;
+  const int col = zrole ? threadIdx.x - WS_NCOL : threadIdx.x;
+
+  long long off[WS_LOADS];
+#pragma unroll
+  for (int l = 0; l < WS_LOADS; ++l) {
+    const int s = col + l * WS_NCOL;
+    const int lx = s % HX, ly = s / HX;
+    int x = (x0 - 2 + lx) % g.nx;
+    x += (x < 0) ? g.nx : 0;
+    int y = (y0 - 2 + ly) % g.ny;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
+  }
+  const int cxg = x0 + col % TX, cyg = y0 + col / TX;
+  const bool col_valid = cxg < g.nx && cyg < g.ny;
+  const long long col_off = (long long)cyg * g.nx + cxg;
+  const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
+  Tc nxt[WS_LOADS][5];
+  if (zrole) {
+    // plane p_first into buffer 0, plane p_first + 1 into registers
+    for (int h = 0; h < 2; ++h) {
+      int z = p_first + h;
+      z += (z < 0) ? g.nz : 0;
+      z -= (z >= g.nz) ? g.nz : 0;
+      const long long zo = (long long)z * g.plane;
+#pragma unroll
+      for (int l = 0; l < WS_LOADS; ++l) {
+        const int s = col + l * WS_NCOL;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) nxt[l][f] = s < WS_NPL ? load_as<Tc>(K.q[f * g.N + zo + off[l]]) : Tc(1);
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int l = 0; l < WS_LOADS; ++l) {
+          const int s = col + l * WS_NCOL;
+          if (s < WS_NPL) {
+            Tc f[NF];
+            primitives(nxt[l], f, K.c);
+#pragma unroll
+            for (int m = 0; m < NF; ++m) lds[0][m * WS_NPL + s] = f[m];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  ZCtx<Tc> zc;
+  QRing6<Tq> qr;
+  const int T = p_last + 1 - p_first + 1;  // one more step than planes: the last emission
+#define TGV_WS_STEP(PH)                                                                                          \
+  {                                                                                                              \
+    const int tt = t + PH, pp = p_first + tt;                                                                    \
+    if (!zrole) {                                                                                                \
+      if (pp <= p_last) ip_step<Tc, SPLIT>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
+    } else {                                                                                                     \
+      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
+                                                    ring_r[(tt + 1) % RR_SLOTS], ring_a[(tt + 1) % RA_SLOTS],    \
+                                                    tt >= 1, nxt, off, pp, z0, z1, p_last, col_valid, col_off, col); \
+    }                                                                                                            \
+    __syncthreads();                                                                                             \
+  }
+  for (int t = 0; t < T; t += WL) {
+    TGV_WS_STEP(0)
+    if (t + 1 >= T) break;
+    TGV_WS_STEP(1)
+    if (t + 2 >= T) break;
+    TGV_WS_STEP(2)
+    if (t + 3 >= T) break;
+    TGV_WS_STEP(3)
+    if (t + 4 >= T) break;
+    TGV_WS_STEP(4)
+    if (t + 5 >= T) break;
+    TGV_WS_STEP(5)
+  }
+#undef TGV_WS_STEP
+}
+
 }  // namespace
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
                         hipStream_t st) {
+  constexpr bool kWs = sizeof(Tc) == 8;  // FP64 arithmetic: warp-specialised kernel
   const int tiles_x = (g.nx + TX - 1) / TX;
-  const int tiles_y = (g.ny + TY - 1) / TY;
+  const int tiles_y = (g.ny + (kWs ? WS_TY : TY) - 1) / (kWs ? WS_TY : TY);
   // Planes per block: long z-marches amortise the 4 halo planes a block
   // loads at its ends, but the grid must still hold enough blocks to fill
   // the chip several times over.
@@ -570,8 +881,12 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
-  hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K, rk,
-                     tiles_x, tiles_y, kz, remap);
+  if constexpr (kWs)
+    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(WS_NT), 0, st, K,
+                       rk, tiles_x, tiles_y, kz, remap);
+  else
+    hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K,
+                       rk, tiles_x, tiles_y, kz, remap);
   return hipGetLastError();
 }
 
