@@ -27,8 +27,9 @@
 // of tiles and their halo re-reads hit that XCD's L2.  Outputs are streamed
 // with the nontemporal hint.  The other split forms of the convective term
 // (Sec. 2.3.1, compared in Sec. 4.2) replace the grouped fluxes by a generic
-// seven-term combination (split_convection).  FP64-arithmetic instances use
-// a warp-specialised variant of the same step (residual_ws, below).
+// seven-term combination (split_convection).  Most instances run the
+// warp-specialised variant of the same step (residual_ws, below); the kernel
+// choice per precision form is made in launch_tiled.
 //
 // Every 4th-order stencil is taken as S(f) = 8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2})
 // (times 1/(12 h)) and S2(f) = 16 (f_{+1} + f_{-1} - 2 f_0) - (f_{+2} + f_{-2} - 2 f_0)
@@ -128,10 +129,10 @@ struct LdsNb {
 
 // The 10 fields of one z-window slot: stored, or re-derived from
 // (rho, m, rho E, 1/rho) exactly as primitives() derives them.
-template <class Tc>
+template <class Tc, bool FULL = kFullWindow<Tc>>
 __device__ __forceinline__ Tc derived(const Tc* w, int f, const Coef<Tc>& c) {
   if (f < 5) return w[f];
-  if constexpr (kFullWindow<Tc>) return w[f + 1];
+  if constexpr (FULL) return w[f + 1];
   if (f < F_P) return w[f - 4] * w[W_IR];
   const Tc u = w[1] * w[W_IR], v = w[2] * w[W_IR], x = w[3] * w[W_IR];
   const Tc p = c.gm1 * (w[4] - Tc(0.5) * (w[1] * u + w[2] * v + w[3] * x));
@@ -558,30 +559,39 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 
 
 // ---------------------------------------------------------------------------
-// Warp-specialised variant, used for the FP64-arithmetic instances.  A block
-// of 2 x 256 threads owns a 64 x 4 tile: threads [0, 256) take the in-plane
-// role, threads [256, 512) the z role, one column each, so that each SIMD
-// holds one wave of each kind and the LDS-heavy in-plane phase of one
-// overlaps the FP64 arithmetic of the other.  At step t (plane p = p_first + t):
+// Warp-specialised variant.  A block of 2 x NCOL threads owns a 64 x WTY
+// tile (WTY = 4 for FP64 arithmetic, 8 for FP32): threads [0, NCOL) take the
+// in-plane role, threads [NCOL, 2 NCOL) the z role, one column each, so that
+// each SIMD holds waves of both kinds and the LDS-heavy in-plane phase of one
+// overlaps the arithmetic of the other.  At step t (plane p = p_first + t):
 //   in-plane: x/y terms of plane p from LDS buffer t % 2 -> partial R into ring
 //             slot t % 4 and the gradient combinations into slot t % 2;
 //   z:        primitives of plane p + 1 into LDS buffer (t + 1) % 2, loads of
 //             plane p + 2, own column of plane p into window slot t % 6, the
 //             combinations of plane p - 1 from the ring, and the emission of
 //             plane p - 3 (z terms, z-mixed terms, store or RK stage).
-// One barrier per step (double-buffered plane).  Measured at 512^3: FP64
-// fused stage 5 % faster than the single-role kernel above; the FP32 forms
-// are faster with the single-role kernel (larger tile, less halo work).
-constexpr int WS_TY = 4, WS_NCOL = TX * WS_TY, WS_NT = 2 * WS_NCOL;
-constexpr int WS_HY = WS_TY + 4, WS_NPL = HX * WS_HY;
-constexpr int WS_LOADS = (WS_NPL + WS_NCOL - 1) / WS_NCOL;
+// One barrier per step (double-buffered plane).
+template <int WTY>
+struct Ws {
+  static constexpr int TY = WTY, NCOL = TX * WTY, NT = 2 * NCOL, HY = WTY + 4, NPL = HX * HY;
+  static constexpr int LOADS = (NPL + NCOL - 1) / NCOL;
+};
+#define TGV_WS_DIMS                                                                          \
+  constexpr int WS_TY = Ws<WTY>::TY, WS_NCOL = Ws<WTY>::NCOL, WS_NPL = Ws<WTY>::NPL;     \
+  constexpr int WS_LOADS = Ws<WTY>::LOADS;                                                 \
+  (void)WS_TY;                                                                               \
+  (void)WS_LOADS;
+
+// The warp-specialised kernel keeps the reduced window (conserved variables
+// and 1/rho) in every precision: its z role has half the registers.
+constexpr int NWS = 6;
 
 template <class Tc, int A, int B, int C, int D>
 struct WinNb6 {
-  const Tc (&W)[6][NW<Tc>];
+  const Tc (&W)[6][NWS];
   const Coef<Tc>& c;
   __device__ __forceinline__ Tc operator()(int f, int s) const {
-    return derived(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
+    return derived<Tc, false>(s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D], f, c);
   }
   __device__ __forceinline__ Tc ir(int s) const { return (s == 0 ? W[A] : s == 1 ? W[B] : s == 2 ? W[C] : W[D])[W_IR]; }
 };
@@ -591,7 +601,7 @@ constexpr int RR_SLOTS = 4, RA_SLOTS = 2;
 
 template <class Tc>
 struct ZCtx {
-  Tc W[WL][NW<Tc>];
+  Tc W[WL][NWS];
   Tc A[WL][3];
 };
 
@@ -600,8 +610,9 @@ struct QRing6 {
   Tq v[WL][5];
 };
 
-template <class Tc, int SPLIT>
+template <class Tc, int SPLIT, int WTY>
 __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ring_r, Tc* ring_a, int col) {
+  TGV_WS_DIMS
   const int tx = col % TX, ty = col / TX;
   const int own = (ty + 2) * HX + (tx + 2);
   Tc c0[NF];
@@ -652,12 +663,13 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
   for (int a = 0; a < 3; ++a) ring_a[a * WS_NCOL + col] = A3[a];
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int PH>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTY, int PH>
 __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, ZCtx<Tc>& zc,
                                        QRing6<Tq>& qr, const Tc* cur, Tc* next, const Tc* ring_r,
-                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[WS_LOADS][5],
-                                       const long long (&off)[WS_LOADS], int p, int z0, int z1, int p_last,
+                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[Ws<WTY>::LOADS][5],
+                                       const long long (&off)[Ws<WTY>::LOADS], int p, int z0, int z1, int p_last,
                                        bool col_valid, long long col_off, int zt) {
+  TGV_WS_DIMS
   constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   const Grid& g = K.g;
   const Coef<Tc>& c = K.c;
@@ -706,10 +718,6 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
 #pragma unroll
     for (int m = 0; m < 5; ++m) zc.W[PH][m] = c0[m];
     zc.W[PH][W_IR] = recip(c0[F_RHO]);
-    if constexpr (kFullWindow<Tc>) {
-#pragma unroll
-      for (int m = F_U; m < NF; ++m) zc.W[PH][m + 1] = c0[m];
-    }
     if (FUSED && !kQinFromWindow && p >= z0 && p < z1 && col_valid) {
       const long long id = (long long)p * g.plane + col_off;
 #pragma unroll
@@ -731,7 +739,7 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
     Tc Gz[3] = {0, 0, 0};
     Tc ck[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) ck[f] = derived(zc.W[K0], f, c);
+    for (int f = 0; f < NF; ++f) ck[f] = derived<Tc, false>(zc.W[K0], f, c);
     direction_terms<Tc, 2, SPLIT>(WinNb6<Tc, KM2, KM1, KP1, KP2>{zc.W, c}, ck, zc.W[K0][W_IR], c, Rz, Gz);
     if (c.viscous) {
       const Tc* u0 = ck + F_U;
@@ -771,9 +779,10 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   }
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
-__global__ void __launch_bounds__(WS_NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTY>
+__global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
                                                                       int tiles_x, int tiles_y, int kz, int remap) {
+  TGV_WS_DIMS
   __shared__ Tc lds[2][NF * WS_NPL];
   __shared__ Tc ring_r[RR_SLOTS][5 * WS_NCOL];
   __shared__ Tc ring_a[RA_SLOTS][3 * WS_NCOL];
@@ -841,9 +850,9 @@ __global__ void __launch_bounds__(WS_NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq,
   {                                                                                                              \
     const int tt = t + PH, pp = p_first + tt;                                                                    \
     if (!zrole) {                                                                                                \
-      if (pp <= p_last) ip_step<Tc, SPLIT>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
+      if (pp <= p_last) ip_step<Tc, SPLIT, WTY>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
     } else {                                                                                                     \
-      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
+      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, WTY, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
                                                     ring_r[(tt + 1) % RR_SLOTS], ring_a[(tt + 1) % RA_SLOTS],    \
                                                     tt >= 1, nxt, off, pp, z0, z1, p_last, col_valid, col_off, col); \
     }                                                                                                            \
@@ -870,9 +879,17 @@ __global__ void __launch_bounds__(WS_NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq,
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
                         hipStream_t st) {
-  constexpr bool kWs = sizeof(Tc) == 8;  // FP64 arithmetic: warp-specialised kernel
+  // Kernel choice (measured at 512^3): the warp-specialised kernel, on 64 x 4
+  // tiles for FP64 arithmetic (registers) and 64 x 8 tiles for FP32
+  // arithmetic; the single-role kernel for two forms where it is faster: the
+  // fused stage with FP64 Q and FP32 arithmetic (its Q_in ring does not fit
+  // the z role's registers) and FP32 Q with FP64 arithmetic.
+  constexpr bool kQinExact = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
+  constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8) && !(sizeof(Tc) == 8 && sizeof(Tq) < 8);
+  constexpr int kWty = sizeof(Tc) == 8 ? 4 : 8;
+  constexpr int kTy = kWs ? kWty : TY;
   const int tiles_x = (g.nx + TX - 1) / TX;
-  const int tiles_y = (g.ny + (kWs ? WS_TY : TY) - 1) / (kWs ? WS_TY : TY);
+  const int tiles_y = (g.ny + kTy - 1) / kTy;
   // Planes per block: long z-marches amortise the 4 halo planes a block
   // loads at its ends, but the grid must still hold enough blocks to fill
   // the chip several times over.
@@ -882,8 +899,8 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
   if constexpr (kWs)
-    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(WS_NT), 0, st, K,
-                       rk, tiles_x, tiles_y, kz, remap);
+    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWty>), dim3((unsigned)nb), dim3(Ws<kWty>::NT),
+                       0, st, K, rk, tiles_x, tiles_y, kz, remap);
   else
     hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K,
                        rk, tiles_x, tiles_y, kz, remap);
