@@ -82,26 +82,48 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
-def copy_ceiling(gib=4, reps=5):
-    """Achieved bandwidth of a plain device-to-device copy (torch copy_ of
-    `gib` GiB, read + write bytes over the event-timed duration): the
-    practical streaming ceiling the stencil kernels are compared with."""
+def attainable(n, reps=5):
+    """Attainable streaming rates, from the hand-written probes of
+    libtgv_probe.so (read + write bytes over the event-timed duration): a
+    plain 4 GiB copy, and the fused FP64 stage's memory traffic at n^3 in its
+    z-march order (no halo, no arithmetic), with 128 and with 16 planes per
+    block."""
+    import ctypes
     import torch
-    n = gib * (1 << 30) // 8
-    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    path = os.path.join(ROOT, "paper_2505_20911_amd", "libtgv_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    lib.tgv_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_void_p]
+    lib.tgv_probe_stage_stream.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def rate(call, nbytes):
+        if call() != 0:
+            raise RuntimeError("stream probe launch failed")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            call()
+        b.record()
+        torch.cuda.synchronize()
+        return nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+
+    out = {}
+    m = 4 * (1 << 30)
+    x = torch.ones(m // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    y.copy_(x)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        y.copy_(x)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
+    out["copy_gbs"] = rate(lambda: lib.tgv_probe_copy(x.data_ptr(), y.data_ptr(), m, st), 2 * m)
     del x, y
+    q = [torch.zeros(5 * n ** 3, dtype=torch.float64, device="cuda") for _ in range(3)]
+    for kz in (128, 16):
+        out[f"stage_pattern_kz{kz}_gbs"] = rate(
+            lambda: lib.tgv_probe_stage_stream(n, kz, 8, q[0].data_ptr(), q[1].data_ptr(), q[2].data_ptr(), st),
+            20 * 8 * n ** 3)
+    del q
     torch.cuda.empty_cache()
-    return 2 * n * 8 / (ms * 1e-3) / 1e9
+    return out
 
 
 def nbytes(dtype):
@@ -348,8 +370,9 @@ def main():
             r = results[key]
             ks = ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['gbs']:.0f} GB/s" for k, v in r["kernels"].items())
             print(f"[bench] {key}: {r['mpt_stage_per_s']:.0f} Mpt.stage/s ({ks})", file=sys.stderr, flush=True)
-    copy_gbs = copy_ceiling()
-    print(f"[bench] device copy ceiling {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    att = attainable(n)
+    print("[bench] attainable streaming: " + ", ".join(f"{k} {v:.0f}" for k, v in att.items()), file=sys.stderr,
+          flush=True)
     head_key = "DP" if "DP" in results else next(iter(results))
     head = results[head_key]
     for key, r in results.items():
@@ -379,7 +402,8 @@ def main():
                      "traffic": measured_traffic(("ns_residual_rk_stage" if kname == "fused" else "ns_residual")
                                                  + f"/{head_key}/{n}"),
                      "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"],
-                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy": hk["gbs"] / copy_gbs},
+                     "attainable": att,
+                     "frac_of_stage_pattern": hk["gbs"] / max(v for k, v in att.items() if k.startswith("stage"))},
         "forms": results,
     }
     if not args.no_adjoint:

@@ -1,7 +1,9 @@
 """Build libtgv.so (the HIP kernels and the C-ABI) in-tree for gfx950.
 
 Each .hip source is compiled to an object with hipcc (in parallel), then the
-objects are linked into paper_2505_20911_amd/libtgv.so.  Packed-FP32 VALU
+objects are linked into paper_2505_20911_amd/libtgv.so.  The streaming
+probes that the benchmark compares the step kernels with (stream_probe.hip)
+go into a library of their own, libtgv_probe.so.  Packed-FP32 VALU
 instructions are disabled for all device code, and multiply-add contraction is
 limited to single source expressions (-ffp-contract=on) so that the same
 expression rounds identically wherever it is inlined.
@@ -19,9 +21,11 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "libtgv")
 LIB = os.path.join(PKG, "libtgv.so")
+PROBE_LIB = os.path.join(PKG, "libtgv_probe.so")
 ARCH = os.environ.get("TGV_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.hip", "init.hip", "residual_tiled.hip", "rk_stage.hip", "integrals.hip", "adjoint.hip"]
+PROBE_SOURCES = ["stream_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -56,17 +60,23 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+def _link(lib: str, objs: list[str], verbose: bool) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + PROBE_SOURCES
+    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    _link(LIB, objs[:len(SOURCES)], verbose)
+    _link(PROBE_LIB, objs[len(SOURCES):], verbose)
     return LIB
 
 

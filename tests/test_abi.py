@@ -148,3 +148,21 @@ def test_last_error_is_per_thread():
         t.join()
     assert msgs["shape"][0] == NS_ERR_SHAPE and b"n[0]" in msgs["shape"][1]
     assert msgs["align"][0] == NS_ERR_ALIGN and b"aligned" in msgs["align"][1]
+
+
+def test_stream_probe_library_loads_and_validates_on_the_host():
+    """The benchmark's streaming probes live in libtgv_probe.so, apart from the
+    method's library; bad arguments are rejected before any launch."""
+    path = os.path.join(ROOT, "paper_2505_20911_amd", "libtgv_probe.so")
+    lib = ctypes.CDLL(path)
+    lib.tgv_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_void_p]
+    lib.tgv_probe_stage_stream.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
+    assert lib.tgv_probe_copy(None, ctypes.c_void_p(0x1000), 16, None) == -1
+    assert lib.tgv_probe_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 24, None) == -1  # not 16-byte
+    assert lib.tgv_probe_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, None) == -1  # misaligned
+    assert lib.tgv_probe_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 0, None) == 0  # nothing to do
+    a, b, c = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))
+    assert lib.tgv_probe_stage_stream(0, 16, 8, a, b, c, None) == -1
+    assert lib.tgv_probe_stage_stream(64, 0, 8, a, b, c, None) == -1
+    assert lib.tgv_probe_stage_stream(64, 16, 3, a, b, c, None) == -1
+    assert lib.tgv_probe_stage_stream(64, 16, 8, None, b, c, None) == -1
