@@ -3,7 +3,7 @@
 // fields.  Everything -- loads, the 4th-order velocity gradient and the
 // accumulation -- is FP64 whatever the storage type of Q.
 //
-// Pass 1 marches a 64 x 4 tile of (x, y) columns along z, like the residual
+// Pass 1 marches a 64 x 4 tile of (x, y) columns along z, as the residual
 // kernel: each plane of the tile plus a 2-point halo is loaded once (rho and
 // the momenta, coalesced along x), turned into velocities in LDS, and each
 // thread takes the in-plane parts of the vorticity at its own column from

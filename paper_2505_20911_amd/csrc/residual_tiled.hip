@@ -559,8 +559,8 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 
 
 // ---------------------------------------------------------------------------
-// Warp-specialised variant.  A block of 2 x NCOL threads owns a 64 x WTY
-// tile (WTY = 4 for FP64 arithmetic, 8 for FP32): threads [0, NCOL) take the
+// Warp-specialised variant.  A block of 2 x NCOL threads owns a WTX x WTY
+// tile (32 x 8 for FP64 arithmetic, 64 x 8 for FP32): threads [0, NCOL) take the
 // in-plane role, threads [NCOL, 2 NCOL) the z role, one column each, so that
 // each SIMD holds waves of both kinds and the LDS-heavy in-plane phase of one
 // overlaps the arithmetic of the other.  At step t (plane p = p_first + t):
@@ -571,14 +571,16 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 //             combinations of plane p - 1 from the ring, and the emission of
 //             plane p - 3 (z terms, z-mixed terms, store or RK stage).
 // One barrier per step (double-buffered plane).
-template <int WTY>
+template <int WTX, int WTY>
 struct Ws {
-  static constexpr int TY = WTY, NCOL = TX * WTY, NT = 2 * NCOL, HY = WTY + 4, NPL = HX * HY;
+  static constexpr int TX = WTX, HX = WTX + 4, TY = WTY, NCOL = WTX * WTY, NT = 2 * NCOL, HY = WTY + 4,
+                       NPL = HX * HY;
   static constexpr int LOADS = (NPL + NCOL - 1) / NCOL;
 };
 #define TGV_WS_DIMS                                                                          \
-  constexpr int WS_TY = Ws<WTY>::TY, WS_NCOL = Ws<WTY>::NCOL, WS_NPL = Ws<WTY>::NPL;     \
-  constexpr int WS_LOADS = Ws<WTY>::LOADS;                                                 \
+  constexpr int WS_TX = Ws<WTX, WTY>::TX, WS_HX = Ws<WTX, WTY>::HX, WS_TY = Ws<WTX, WTY>::TY;     \
+  constexpr int WS_NCOL = Ws<WTX, WTY>::NCOL, WS_NPL = Ws<WTX, WTY>::NPL;                 \
+  constexpr int WS_LOADS = Ws<WTX, WTY>::LOADS;                                            \
   (void)WS_TY;                                                                               \
   (void)WS_LOADS;
 
@@ -610,11 +612,11 @@ struct QRing6 {
   Tq v[WL][5];
 };
 
-template <class Tc, int SPLIT, int WTY>
+template <class Tc, int SPLIT, int WTX, int WTY>
 __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ring_r, Tc* ring_a, int col) {
   TGV_WS_DIMS
-  const int tx = col % TX, ty = col / TX;
-  const int own = (ty + 2) * HX + (tx + 2);
+  const int tx = col % WS_TX, ty = col / WS_TX;
+  const int own = (ty + 2) * WS_HX + (tx + 2);
   Tc c0[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) c0[k] = lds[k * WS_NPL + own];
@@ -624,7 +626,7 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
   {
     Tc Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0};  // D_x u_a, D_y u_a
     direction_terms<Tc, 0, SPLIT>(LdsNb<Tc, 1, WS_NPL>{lds, own}, c0, ir0, c, R, Gx);
-    direction_terms<Tc, 1, SPLIT>(LdsNb<Tc, HX, WS_NPL>{lds, own}, c0, ir0, c, R, Gy);
+    direction_terms<Tc, 1, SPLIT>(LdsNb<Tc, WS_HX, WS_NPL>{lds, own}, c0, ir0, c, R, Gy);
     A3[0] = Gx[2];
     A3[1] = Gy[2];
     A3[2] = Gx[0] + Gy[1];
@@ -640,15 +642,15 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
     Tc iv[4], iu[4];
 #pragma unroll
     for (int sy = 0; sy < 4; ++sy) {
-      const int row = own + offs[sy] * HX;
+      const int row = own + offs[sy] * WS_HX;
       iv[sy] = S1(lds[(F_U + 1) * WS_NPL + row - 2], lds[(F_U + 1) * WS_NPL + row - 1], lds[(F_U + 1) * WS_NPL + row + 1],
                   lds[(F_U + 1) * WS_NPL + row + 2]);
     }
 #pragma unroll
     for (int sx = 0; sx < 4; ++sx) {
       const int cl = own + offs[sx];
-      iu[sx] = S1(lds[F_U * WS_NPL + cl - 2 * HX], lds[F_U * WS_NPL + cl - HX], lds[F_U * WS_NPL + cl + HX],
-                  lds[F_U * WS_NPL + cl + 2 * HX]);
+      iu[sx] = S1(lds[F_U * WS_NPL + cl - 2 * WS_HX], lds[F_U * WS_NPL + cl - WS_HX], lds[F_U * WS_NPL + cl + WS_HX],
+                  lds[F_U * WS_NPL + cl + 2 * WS_HX]);
     }
     const Tc cxy = c.c1[0] * c.c1[1] * c.ire * Tc(1.0 / 3.0);
     const Tc mx = cxy * S1(iv[0], iv[1], iv[2], iv[3]);
@@ -663,11 +665,11 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
   for (int a = 0; a < 3; ++a) ring_a[a * WS_NCOL + col] = A3[a];
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTY, int PH>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int PH>
 __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, ZCtx<Tc>& zc,
                                        QRing6<Tq>& qr, const Tc* cur, Tc* next, const Tc* ring_r,
-                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[Ws<WTY>::LOADS][5],
-                                       const long long (&off)[Ws<WTY>::LOADS], int p, int z0, int z1, int p_last,
+                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[Ws<WTX, WTY>::LOADS][5],
+                                       const long long (&off)[Ws<WTX, WTY>::LOADS], int p, int z0, int z1, int p_last,
                                        bool col_valid, long long col_off, int zt) {
   TGV_WS_DIMS
   constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
@@ -710,8 +712,8 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   }
   // 2. own column of plane p into window slot PH
   if (p <= p_last) {
-    const int tx = zt % TX, ty = zt / TX;
-    const int own = (ty + 2) * HX + (tx + 2);
+    const int tx = zt % WS_TX, ty = zt / WS_TX;
+    const int own = (ty + 2) * WS_HX + (tx + 2);
     Tc c0[NF];
 #pragma unroll
     for (int m = 0; m < NF; ++m) c0[m] = cur[m * WS_NPL + own];
@@ -779,8 +781,8 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   }
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTY>
-__global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY>
+__global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
                                                                       int tiles_x, int tiles_y, int kz, int remap) {
   TGV_WS_DIMS
   __shared__ Tc lds[2][NF * WS_NPL];
@@ -793,7 +795,7 @@ __global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kern
   const int tx_t = b % tiles_x;
   const int ty_t = (b / tiles_x) % tiles_y;
   const int cz = b / (tiles_y * tiles_x);
-  const int x0 = tx_t * TX, y0 = ty_t * WS_TY;
+  const int x0 = tx_t * WS_TX, y0 = ty_t * WS_TY;
   const int z0 = cz * kz;
   const int z1 = min(z0 + kz, g.nz);
   const bool zrole = threadIdx.x >= WS_NCOL;
@@ -803,14 +805,14 @@ __global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kern
 #pragma unroll
   for (int l = 0; l < WS_LOADS; ++l) {
     const int s = col + l * WS_NCOL;
-    const int lx = s % HX, ly = s / HX;
+    const int lx = s % WS_HX, ly = s / WS_HX;
     int x = (x0 - 2 + lx) % g.nx;
     x += (x < 0) ? g.nx : 0;
     int y = (y0 - 2 + ly) % g.ny;
     y += (y < 0) ? g.ny : 0;
     off[l] = (long long)y * g.nx + x;
   }
-  const int cxg = x0 + col % TX, cyg = y0 + col / TX;
+  const int cxg = x0 + col % WS_TX, cyg = y0 + col / WS_TX;
   const bool col_valid = cxg < g.nx && cyg < g.ny;
   const long long col_off = (long long)cyg * g.nx + cxg;
   const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
@@ -850,9 +852,9 @@ __global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kern
   {                                                                                                              \
     const int tt = t + PH, pp = p_first + tt;                                                                    \
     if (!zrole) {                                                                                                \
-      if (pp <= p_last) ip_step<Tc, SPLIT, WTY>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
+      if (pp <= p_last) ip_step<Tc, SPLIT, WTX, WTY>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
     } else {                                                                                                     \
-      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, WTY, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
+      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, WTX, WTY, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
                                                     ring_r[(tt + 1) % RR_SLOTS], ring_a[(tt + 1) % RA_SLOTS],    \
                                                     tt >= 1, nxt, off, pp, z0, z1, p_last, col_valid, col_off, col); \
     }                                                                                                            \
@@ -879,16 +881,18 @@ __global__ void __launch_bounds__(Ws<WTY>::NT, kWavesPerEU<Tc>) residual_ws(Kern
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
                         hipStream_t st) {
-  // Kernel choice (measured at 512^3): the warp-specialised kernel, on 64 x 4
-  // tiles for FP64 arithmetic (registers) and 64 x 8 tiles for FP32
-  // arithmetic; the single-role kernel for two forms where it is faster: the
-  // fused stage with FP64 Q and FP32 arithmetic (its Q_in ring does not fit
-  // the z role's registers) and FP32 Q with FP64 arithmetic.
+  // Kernel choice (measured at 512^3 and 1024^3): the warp-specialised
+  // kernel, on 32 x 8 tiles for FP64 arithmetic (256 columns per role, as
+  // many as the registers allow; narrower than 64 so that fewer halo rows
+  // are loaded per point) and 64 x 8 tiles for FP32 arithmetic; the
+  // single-role kernel for two forms where it is faster: the fused stage
+  // with FP64 Q and FP32 arithmetic (its Q_in ring does not fit the z role's
+  // registers) and FP32 Q with FP64 arithmetic.
   constexpr bool kQinExact = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8) && !(sizeof(Tc) == 8 && sizeof(Tq) < 8);
-  constexpr int kWty = sizeof(Tc) == 8 ? 4 : 8;
-  constexpr int kTy = kWs ? kWty : TY;
-  const int tiles_x = (g.nx + TX - 1) / TX;
+  constexpr int kWtx = sizeof(Tc) == 8 ? 32 : 64, kWty = 8;
+  constexpr int kTx = kWs ? kWtx : TX, kTy = kWs ? kWty : TY;
+  const int tiles_x = (g.nx + kTx - 1) / kTx;
   const int tiles_y = (g.ny + kTy - 1) / kTy;
   // Planes per block: long z-marches amortise the 4 halo planes a block
   // loads at its ends, but the grid must still hold enough blocks to fill
@@ -899,8 +903,8 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
   if constexpr (kWs)
-    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWty>), dim3((unsigned)nb), dim3(Ws<kWty>::NT),
-                       0, st, K, rk, tiles_x, tiles_y, kz, remap);
+    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty>), dim3((unsigned)nb),
+                       dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
   else
     hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K,
                        rk, tiles_x, tiles_y, kz, remap);
