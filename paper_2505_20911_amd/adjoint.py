@@ -42,8 +42,10 @@ class CheckpointedDissipation:
         self.device = torch.device(device)
         shape, dt_ = params.shape, prec.q
         mk = lambda: torch.empty(shape, dtype=dt_, device=self.device)
-        self.cur, self.qt, self.r = mk(), torch.zeros(shape, dtype=dt_, device=self.device), mk()
-        self.Y = [mk(), mk(), mk()]
+        # Forward steps run the fused residual + stage kernel, ping-ponging
+        # between `cur` and `alt`; Q~ is updated in place.
+        self.cur, self.alt, self.qt = mk(), mk(), torch.zeros(shape, dtype=dt_, device=self.device)
+        self.Y = [None, mk(), mk()]  # stage inputs of the step being reversed (Y[0] is `cur`)
         self.qbar, self.zeta, self.rbar = mk(), mk(), mk()
         self.snap = [mk() for _ in range(self.slots)]
         self.qlast = mk()
@@ -61,11 +63,22 @@ class CheckpointedDissipation:
         return 0.5 if n in (0, self.l) else 1.0
 
     # -- forward pieces
-    def _advance(self, q: torch.Tensor) -> None:
-        for i in range(3):
-            tgv.ns_residual(self.params, self.prec, q, self.r)
-            tgv.rk_stage(self.params, self.prec, i, self.dt, q, self.qt, self.r)
+    def _stage(self, i: int, q_in: torch.Tensor, q_out: torch.Tensor) -> None:
+        tgv.ns_residual_rk_stage(self.params, self.prec, i, self.dt, q_in, q_out, self.qt)
+
+    def _step(self, q: torch.Tensor) -> torch.Tensor:
+        """One RK3 step from q (left unchanged only if it is not `alt`);
+        returns the buffer that holds the result, which is `alt` on entry."""
+        a, b = q, self.alt
+        self._stage(0, a, b)
+        self._stage(1, b, a)
+        self._stage(2, a, b)
+        self.alt = a
         self.advances += 1
+        return b
+
+    def _advance(self) -> None:
+        self.cur = self._step(self.cur)
 
     def _integrals(self, q: torch.Tensor, n: int) -> None:
         tgv.flow_integrals(self.params, self.prec, q, self.iwork, self.eps[n])
@@ -85,7 +98,7 @@ class CheckpointedDissipation:
                 self._pos = k
                 break
             if act[0] == "advance":
-                self._advance(self.cur)
+                self._advance()
                 n += 1
                 self._integrals(self.cur, n)
             elif act[0] == "store":
@@ -93,8 +106,9 @@ class CheckpointedDissipation:
             elif act[0] in ("restore", "free"):  # cannot occur before the first reversal
                 raise AssertionError(act)
         if self.l > 0:
-            self.qlast.copy_(self.cur)  # Q^{l-1}; advance a copy to Q^l for eps^S(Q^l)
-            self._advance(self.qlast)
+            # Q^{l-1} -> Q^l in `qlast` for eps^S(Q^l), keeping Q^{l-1} in `cur`
+            self.qlast.copy_(self.cur)
+            self.qlast = self._step(self.qlast)
             self._integrals(self.qlast, self.l)
         eps = self.eps[:, 2].cpu().numpy()
         w = np.ones(self.l + 1)
@@ -103,11 +117,12 @@ class CheckpointedDissipation:
 
     # -- reverse pieces
     def _reverse_step(self, n: int, scale: float) -> None:
-        """Reverse step n; the current state is Q^{n-1}."""
-        for i in range(3):
-            self.Y[i].copy_(self.cur)
-            tgv.ns_residual(self.params, self.prec, self.cur, self.r)
-            tgv.rk_stage(self.params, self.prec, i, self.dt, self.cur, self.qt, self.r)
+        """Reverse step n; the current state is Q^{n-1}.  Only the stage
+        inputs Y_0 = Q^{n-1}, Y_1, Y_2 are needed (not Q^n), and the schedule
+        restores a snapshot after every reversal, so `cur` is left at Q^{n-1}."""
+        self.Y[0] = self.cur
+        self._stage(0, self.Y[0], self.Y[1])
+        self._stage(1, self.Y[1], self.Y[2])
         for i in (2, 1, 0):
             tgv.rk_stage_adjoint(self.params, self.prec, i, self.dt, self.qbar, self.zeta, self.rbar)
             tgv.ns_residual_adjoint(self.params, self.prec, self.Y[i], self.rbar, self.qbar, self.awork)
@@ -126,7 +141,7 @@ class CheckpointedDissipation:
         for act in self.actions[self._pos:]:
             kind = act[0]
             if kind == "advance":
-                self._advance(self.cur)
+                self._advance()
             elif kind == "store":
                 self.snap[act[1]].copy_(self.cur)
             elif kind == "restore":

@@ -38,8 +38,8 @@ def setup():
     J = dissipation(state_from_velocity(uu, rho0, p0, p.gamma), p, tgv.PRESETS["DP"], DT, STEPS, slots=SLOTS)
     J.backward()
     torch.cuda.synchronize()
-    say("FP64 J", float(J), "forward+reverse", time.perf_counter() - t, "s")
-    return p, u0, rho0, p0, uu.grad.detach(), float(J)
+    say("FP64 J", float(J.detach()), "forward+reverse", time.perf_counter() - t, "s")
+    return p, u0, rho0, p0, uu.grad.detach(), float(J.detach())
 
 
 def test_revolve_schedule_cost():
@@ -72,8 +72,8 @@ def test_fp32_gradient_close_to_fp64(setup):
     J.backward()
     g32 = uu.grad.detach().double()
     rel = float(torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64))
-    say("FP32 J", float(J), "FP64 J", J64, "gradient rel L2 difference", rel)
-    assert abs(float(J) - J64) <= 1e-4 * abs(J64)
+    say("FP32 J", float(J.detach()), "FP64 J", J64, "gradient rel L2 difference", rel)
+    assert abs(float(J.detach()) - J64) <= 1e-4 * abs(J64)
     assert rel <= 1e-2
 
 
