@@ -53,3 +53,20 @@ def test_closed_form_matches_recursion():
     # 400 steps, 20 snapshot buffers beside x_0 (21 counting it)
     assert revolve.optimal_advances(400, 20) == 924
     assert revolve.binomial_closed_form(400, 19) == 947
+
+
+def test_every_reversal_is_followed_by_a_restore():
+    """The reverse sweep leaves the current state at the step's input (it
+    recomputes only the stage inputs it needs), which is sound only because a
+    reversal is never followed by an advance or a store before a restore."""
+    for l in range(1, 60):
+        for s in range(1, 12):
+            acts = revolve.schedule(l, s)
+            for a, b in zip(acts, acts[1:]):
+                if a[0] == "reverse":
+                    assert b[0] in ("restore", "free"), (l, s, a, b)
+            k = 0
+            while k < len(acts):
+                if acts[k][0] == "free":
+                    assert k + 1 < len(acts) and acts[k + 1][0] == "restore", (l, s, acts[k:k + 2])
+                k += 1
