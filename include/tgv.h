@@ -152,10 +152,11 @@ size_t flow_integrals_workspace_bytes(const ns_params_t* params);
 int flow_integrals(const ns_params_t* params, const ns_prec_t* prec, const void* q,
                    void* workspace, double* out8, void* stream);
 
-/* Bytes of device workspace ns_residual_adjoint() needs: 19 fields of N values
- * of prec->q's type (velocity, R_bar-weighted viscous fields, the symmetric
- * viscous-work adjoint and the inner differences of the mixed derivatives,
- * read at stencil neighbours by the gather pass). */
+/* Bytes of device workspace ns_residual_adjoint() needs: 18 fields of N values
+ * of prec->q's type (velocity and R_bar-weighted velocity fields, the
+ * symmetric viscous-work adjoint and the inner differences of the mixed
+ * derivatives, read at stencil neighbours by the later passes; only the
+ * viscous residual uses it). */
 size_t ns_residual_adjoint_workspace_bytes(const ns_params_t* params, const ns_prec_t* prec);
 
 /* Discrete adjoint of ns_residual at state q:  q_bar += (dR/dQ)(q)^T r_bar.

@@ -40,10 +40,10 @@ CFLAGS = [
 ]
 
 
-# Per-source scheduling choice: the adjoint gather kernels are bound by load
-# latency; grouping their many global loads into clauses measured 19 % faster
-# in FP32 (unchanged in FP64) at 512^3.
-EXTRA = {"adjoint.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
+# Per-source compiler options (none at present: the default scheduler keeps
+# the adjoint gather within 2 waves' registers per SIMD in FP64, where the
+# memory-clause scheduler spilled it).
+EXTRA: dict[str, list[str]] = {}
 
 
 def _compile(src: str, verbose: bool) -> str:

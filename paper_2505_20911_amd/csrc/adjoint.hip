@@ -5,9 +5,9 @@
 // D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
 // stencil term of the forward residual turns into a stencil of R_bar-weighted
 // pointwise fields evaluated around the output point, plus pointwise terms.
-// Three passes over a caller-provided workspace of 19 fields:
-//   pass 0 (pointwise) stores the fields the gather needs at stencil
-//     neighbours: u_a, V_bar_a = R_bar_{m_a} + R_bar_E u_a and sum_f R_bar_f Q_f;
+// Three passes over a caller-provided workspace of 18 fields:
+//   pass 0 (pointwise, viscous only) stores what pass A reads at stencil
+//     neighbours: u_a and V_bar_a = R_bar_{m_a} + R_bar_E u_a;
 //   pass A (viscous only) stores the adjoint of the viscous work sum
 //     tau_ad G_ad, the symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components),
 //     and the inner derivatives of the mixed second-derivative terms,
@@ -15,7 +15,9 @@
 //     that D_a D_b u_b and (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one
 //     more first difference each in pass B (D_a and D_b commute on the
 //     periodic grid);
-//   pass B gathers every transposed-stencil and pointwise contribution.
+//   pass B gathers every transposed-stencil and pointwise contribution,
+//     re-deriving u_a, V_bar_a and sum_f R_bar_f Q_f at each neighbour from Q
+//     and R_bar (which it loads there anyway) rather than reading them back.
 // 1/rho is the hardware reciprocal refined by Newton-Raphson, as in the
 // forward residual.
 #include "tgv_device.h"
@@ -105,10 +107,10 @@ __device__ __forceinline__ int sym(int a, int d) {
 }
 
 // Workspace layout, fields of N values each.
-enum { W_U = 0, W_VB = 3, W_SRQ = 6, W_GB = 7, W_SIG = 13, W_TAU = 16, W_FIELDS = 19 };
+enum { W_U = 0, W_VB = 3, W_GB = 6, W_SIG = 12, W_TAU = 15, W_FIELDS = 18 };
 static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 
-// Pass 0: pointwise fields read at stencil neighbours by the later passes.
+// Pass 0: pointwise fields read at stencil neighbours by pass A.
 template <class T>
 __global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict__ q, const T* __restrict__ rb,
                                                      T* __restrict__ w) {
@@ -122,16 +124,12 @@ __global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict
     r0[f] = rb[f * N + id];
   }
   const T ir = recip(q0[0]);
-  T srq = 0;
-#pragma unroll
-  for (int f = 0; f < 5; ++f) srq += r0[f] * q0[f];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const T u = q0[a + 1] * ir;
     w[(W_U + a) * N + id] = u;
     w[(W_VB + a) * N + id] = r0[a + 1] + r0[4] * u;
   }
-  w[W_SRQ * N + id] = srq;
 }
 
 // Pass A: G_bar_ad = 2 R_bar_E tau_ad, sigma_a and tau_b at every point.
@@ -185,12 +183,116 @@ __global__ void __launch_bounds__(kThreads) adj_stress(Grid g, ColMarch cm, Coef
 }
 
 // Pass B: gather of all transposed-stencil and pointwise contributions.
+// Along each direction the neighbours are visited in symmetric pairs, (-1, +1)
+// and then (-2, +2).  At each neighbour u_a, V_bar_a and sum_f R_bar_f Q_f are
+// derived from Q and R_bar with the expressions pass 0 uses, and every first
+// and second difference is accumulated pair by pair,
+//   8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2}),
+//   16 ((f_{+1} - f_0) + (f_{-1} - f_0)) - ((f_{+2} - f_0) + (f_{-2} - f_0))
+// (the factors 8 and 16 are exact), the neighbour differences always taken
+// first.  Only the viscous fields G_bar, sigma and tau come from the
+// workspace.
+// The values of Q and R_bar at one neighbour and what is derived from them.
+template <class T>
+struct NbVals {
+  T q[5], r[5], u[3], vb[3], srq;
+};
+
+template <class T>
+__device__ __forceinline__ void load_nb(const T* __restrict__ q, const T* __restrict__ rb, long long N, long long n,
+                                        NbVals<T>& v) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    v.q[f] = q[f * N + n];
+    v.r[f] = rb[f * N + n];
+  }
+  const T ir = recip(v.q[0]);
+  T srq = 0;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) srq += v.r[f] * v.q[f];
+  v.srq = srq;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T u = v.q[a + 1] * ir;
+    v.u[a] = u;
+    v.vb[a] = v.r[a + 1] + v.r[4] * u;
+  }
+}
+
+// Difference sums of one direction (before the 1/(12 h) or 1/(12 h^2) factor).
+// `ubs` collects the terms that enter u_bar_d through a first difference:
+// sum_f (-R_bar_f) D_d q_f + D_d (sum_f R_bar_f Q_f), each difference taken
+// from the neighbour values first.
+template <class T>
+struct DirSums {
+  T r[5], rud[5], ud, ubs, rE2, vb2[3], u2[3], gb[3], sig, tau;
+};
+
+template <int K, class T>
+__device__ __forceinline__ void d1_add(T& acc, T diff) {
+  if (K == 1)
+    acc = T(8) * diff;
+  else
+    acc = acc - diff;
+}
+template <int K, class T>
+__device__ __forceinline__ void d2_add(T& acc, T plus, T minus, T c0) {
+  const T sum = (plus - c0) + (minus - c0);
+  if (K == 1)
+    acc = T(16) * sum;
+  else
+    acc = acc - sum;
+}
+
+// Pair K of direction d: neighbours at -K and +K.
+template <int K, class T>
+__device__ __forceinline__ void add_pair(DirSums<T>& S, const T* __restrict__ q, const T* __restrict__ rb,
+                                         const T* __restrict__ w, long long N, long long nm, long long np, int d,
+                                         bool viscous, const T (&r0)[5], const T (&vb0)[3], const T (&u0)[3]) {
+  {
+    NbVals<T> m, p;
+    load_nb(q, rb, N, nm, m);
+    load_nb(q, rb, N, np, p);
+    const T udm = d == 0 ? m.u[0] : (d == 1 ? m.u[1] : m.u[2]);
+    const T udp = d == 0 ? p.u[0] : (d == 1 ? p.u[1] : p.u[2]);
+    T ubs = p.srq - m.srq;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      d1_add<K>(S.r[f], p.r[f] - m.r[f]);
+      const T pu = p.r[f] * udp;
+      const T mu = m.r[f] * udm;
+      d1_add<K>(S.rud[f], pu - mu);
+      ubs -= r0[f] * (p.q[f] - m.q[f]);
+    }
+    d1_add<K>(S.ud, udp - udm);
+    d1_add<K>(S.ubs, ubs);
+    if (viscous) {
+      d2_add<K>(S.rE2, p.r[4], m.r[4], r0[4]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        d2_add<K>(S.vb2[a], p.vb[a], m.vb[a], vb0[a]);
+        d2_add<K>(S.u2[a], p.u[a], m.u[a], u0[a]);
+      }
+    }
+  }
+  if (viscous) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T* base = w + (W_GB + sym(a, d)) * N;
+      d1_add<K>(S.gb[a], base[np] - base[nm]);
+    }
+    d1_add<K>(S.sig, w[(W_SIG + d) * N + np] - w[(W_SIG + d) * N + nm]);
+    d1_add<K>(S.tau, w[(W_TAU + d) * N + np] - w[(W_TAU + d) * N + nm]);
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ q,
                                                        const T* __restrict__ rb, const T* __restrict__ w,
                                                        T* __restrict__ qbar) {
   const Column col = column(g, cm);
   if (!col.valid) return;
+  const bool viscous = c.viscous != 0;
 #pragma nounroll
   for (int z = col.z0; z < col.z1; ++z) {
     const int ijk[3] = {col.x, col.y, z};
@@ -205,9 +307,12 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef
       r0[f] = rb[f * N + id];
     }
     const T ir0 = recip(q0[0]);
-    T u0[3];
+    T u0[3], vb0[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u0[a] = q0[a + 1] * ir0;
+    for (int a = 0; a < 3; ++a) {
+      u0[a] = q0[a + 1] * ir0;
+      vb0[a] = r0[a + 1] + r0[4] * u0[a];
+    }
     const T p0 = c.gm1 * (q0[4] - half * (q0[1] * u0[0] + q0[2] * u0[1] + q0[3] * u0[2]));
     const T T0 = c.gm2 * p0 * ir0;
 
@@ -216,38 +321,26 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef
     T pb = 0, Tb = 0;
     T lap[3] = {0, 0, 0}, X[3] = {0, 0, 0};  // forward viscous pieces at this point
 
-    const int offs[4] = {-2, -1, 1, 2};
-    // Neighbour values are consumed one field at a time, and the direction
-    // loop is not unrolled, so that few of them are live at once; the
-    // direction's own components are selected, not indexed.
+    // The direction loop is not unrolled, so that one direction's sums and
+    // one pair of neighbours are live at a time.
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
       const T u0d = d == 0 ? u0[0] : (d == 1 ? u0[1] : u0[2]);
-      T ubd = 0, Xd = 0;  // contributions to ub[d], X[d]
-      long long n[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) n[s] = nb(g, id, ijk, d, offs[s]);
-      auto at = [&](const T* base, int s) { return base[n[s]]; };
-      auto D1n = [&](const T* base, T sc) { return D1(at(base, 0), at(base, 1), at(base, 2), at(base, 3), sc); };
       const T s1 = c.c1[d], s2 = c.c2[d];
-      T ud[4];  // u_d at the neighbours
-#pragma unroll
-      for (int s = 0; s < 4; ++s) ud[s] = at(w + (W_U + d) * N, s);
-      const T dud = D1(ud[0], ud[1], ud[2], ud[3], s1);  // forward D_d u_d at this point
+      DirSums<T> S;
+      add_pair<1>(S, q, rb, w, N, nb(g, id, ijk, d, -1), nb(g, id, ijk, d, 1), d, viscous, r0, vb0, u0);
+      add_pair<2>(S, q, rb, w, N, nb(g, id, ijk, d, -2), nb(g, id, ijk, d, 2), d, viscous, r0, vb0, u0);
+      T ubd = 0, Xd = 0;  // contributions to ub[d], X[d]
+      const T dud = s1 * S.ud;  // forward D_d u_d at this point
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
-        T rn[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) rn[s] = at(rb + f * N, s);
-        const T Dr = D1(rn[0], rn[1], rn[2], rn[3], s1);
+        const T Dr = s1 * S.r[f];
         // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
         const T F = half * Dr;
         qb[f] += F * u0d;
         ubd += F * q0[f];
         // (2) u_d D_d q_f
-        qb[f] += half * D1(rn[0] * ud[0], rn[1] * ud[1], rn[2] * ud[2], rn[3] * ud[3], s1);
-        const T dq = D1n(q + f * N, s1);
-        ubd -= half * r0[f] * dq;
+        qb[f] += half * (s1 * S.rud[f]);
         // (3) q_f D_d u_d, pointwise part
         qb[f] -= half * r0[f] * dud;
         // (4) momentum pressure gradient D_d p
@@ -257,31 +350,29 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef
           pb += Dr * u0d;
           ubd += Dr * p0;
           // (8) heat flux
-          if (c.viscous) Tb += c.kap * D2(rn[0], rn[1], r0[4], rn[2], rn[3], s2);
+          if (viscous) Tb += c.kap * (s2 * S.rE2);
         }
       }
-      // (3) q_f D_d u_d, stencil part summed over f
-      ubd += half * D1n(w + W_SRQ * N, s1);
-      if (c.viscous) {
+      // (2) -R_bar_f D_d q_f and (3) q_f D_d u_d, stencil part summed over f
+      ubd += half * (s1 * S.ubs);
+      if (viscous) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
-          const T* vbase = w + (W_VB + a) * N;
-          const T vb = D2(at(vbase, 0), at(vbase, 1), vbase[id], at(vbase, 2), at(vbase, 3), s2);
+          const T vb = s2 * S.vb2[a];
           ub[a] += c.ire * vb;
           if (a == d) ubd += c.ire * (T(1.0 / 3.0)) * vb;
           // forward pieces of V_{m_a} at this point
-          const T* ubase = w + (W_U + a) * N;
-          const T l = D2(at(ubase, 0), at(ubase, 1), u0[a], at(ubase, 2), at(ubase, 3), s2);
+          const T l = s2 * S.u2[a];
           lap[a] += l;
           if (a == d) Xd += l;
           // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
-          ub[a] -= D1n(w + (W_GB + sym(a, d)) * N, s1);
+          ub[a] -= s1 * S.gb[a];
         }
         // (9) mixed second derivatives through the stored inner differences:
         //   forward X_d += D_d sigma_d ; adjoint u_d += (1/(3 Re)) D_d tau_d
-        Xd += D1n(w + (W_SIG + d) * N, s1);
-        ubd += c.ire * T(1.0 / 3.0) * D1n(w + (W_TAU + d) * N, s1);
+        Xd += s1 * S.sig;
+        ubd += c.ire * T(1.0 / 3.0) * (s1 * S.tau);
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -290,7 +381,7 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef
       }
     }
 
-    if (c.viscous) {
+    if (viscous) {
       // pointwise part of sum_a u_a V_{m_a}
 #pragma unroll
       for (int a = 0; a < 3; ++a) ub[a] += r0[4] * (c.ire * (lap[a] + X[a] * T(1.0 / 3.0)));
@@ -399,10 +490,10 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
   const ColMarch cm = col_march(g);
-  hipLaunchKernelGGL((adj_prim<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, qq, rr, w);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (c.viscous) {
+    hipLaunchKernelGGL((adj_prim<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, qq, rr, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adj_stress<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, rr, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -32,7 +32,7 @@ hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q,
                             double* out8, hipStream_t st);
 
 // Fields of N values the residual adjoint's workspace holds.
-constexpr int kResidualAdjointWorkFields = 19;
+constexpr int kResidualAdjointWorkFields = 18;
 
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar,
