@@ -148,3 +148,38 @@ def test_autograd_velocity_gradient_matches_finite_differences():
         ad = float((g * d).sum())
         say("  FD", fd, "AD", ad)
         assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("viscous", [1, 0])
+def test_residual_adjoint_full_size_dot_product(viscous):
+    """The benchmark's launch of ns_residual_adjoint (FP64, 512^3), checked by
+    the adjoint identity <R_bar, J dQ> = <J^T R_bar, dQ>, which holds at any
+    size: J dQ from central differences of the forward residual (itself
+    checked against the oracle at this size on sampled points), eps = 1e-6
+    (truncation and rounding each ~1e-10 relative here; a term missing from
+    the viscous part alone would show at ~1e-4)."""
+    n = 512
+    say("adjoint dot product", n, "viscous", viscous)
+    p = tgv.Params(n=(n, n, n), viscous=viscous)
+    prec = tgv.PRESETS["DP"]
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(20250527 + viscous)
+    draw = lambda: torch.randn(p.shape, generator=gen, dtype=torch.float64, device=DEV)
+    scale = torch.tensor([1.0, 0.1, 0.1, 0.1, 1.0], dtype=torch.float64, device=DEV).view(5, 1, 1, 1)
+    q = torch.empty(p.shape, dtype=torch.float64, device=DEV)
+    tgv.tgv_init(p, q)
+    q += 1e-3 * scale * draw()  # break the Taylor-Green symmetries
+    dq = scale * draw()
+    rbar = draw()
+    eps = 1e-6
+    r_p, r_m = torch.empty_like(q), torch.empty_like(q)
+    tgv.ns_residual(p, prec, q + eps * dq, r_p)
+    tgv.ns_residual(p, prec, q - eps * dq, r_m)
+    r_p -= r_m
+    lhs = float((r_p * rbar).sum()) / (2 * eps)
+    del r_p, r_m
+    qb = torch.zeros_like(q)
+    tgv.ns_residual_adjoint(p, prec, q, rbar, qb, work_for(p, prec, tgv.ns_residual_adjoint_workspace_bytes))
+    rhs = float((qb * dq).sum())
+    say(f"  <R_bar, J dQ> = {lhs:.15e}  <J^T R_bar, dQ> = {rhs:.15e}  rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
