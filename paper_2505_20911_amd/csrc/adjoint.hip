@@ -64,9 +64,8 @@ ColMarch col_march(const Grid& g) {
   ColMarch m;
   m.tiles_x = (g.nx + CX - 1) / CX;
   m.tiles_y = (g.ny + CY - 1) / CY;
-  // 16 planes per block measured 3-5 % faster than 64 or 128 at 512^3 (the
-  // columns' working sets stay in L2 longer); fewer where the grid would
-  // otherwise hold too few blocks to fill the chip
+  // 16 planes per block (measured 3-5 % faster than 64 or 128 at 512^3);
+  // fewer where the grid would otherwise hold too few blocks to fill the chip
   m.kz = 16;
   while (m.kz > 1 && (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz) < 2048) m.kz /= 2;
   m.blocks = (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz);
