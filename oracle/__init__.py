@@ -269,8 +269,8 @@ def velocity_grad_from_state_grad(P: Params, qbar0: np.ndarray, u0: np.ndarray,
 
 
 def residual_at(P: Params, q, idx) -> np.ndarray:
-    """Residual at the listed linear point indices (pointwise evaluation), shape (len(idx), 5)."""
-    _blaisdell_only(P, "residual_at")
+    """Residual at the listed linear point indices (pointwise evaluation, every
+    split form), shape (len(idx), 5)."""
     q = _q(P, q)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     out = np.empty((idx.size, 5), np.float64)

@@ -677,12 +677,38 @@ struct PointEval {
     double u[3];
     for (int a = 0; a < 3; ++a) u[a] = vel(a, i, j, k);
     double out[5] = {0, 0, 0, 0, 0};
+    // phi of conserved component f (rho phi = q_f): 1, u_a, E/rho
+    auto phi = [this](int f, int x, int y, int z) {
+      return f == 0 ? 1.0 : f < 4 ? vel(f - 1, x, y, z) : cons(4, x, y, z) / cons(0, x, y, z);
+    };
     for (int f = 0; f < 5; ++f) {
       double C = 0.0;
       for (int d = 0; d < 3; ++d) {
         auto qu = [&, f, d](int x, int y, int z) { return cons(f, x, y, z) * vel(d, x, y, z); };
-        C += 0.5 * (d1(qu, d, i, j, k) + u[d] * d1(Qf(f), d, i, j, k) +
-                    cons(f, i, j, k) * d1(U(d), d, i, j, k));
+        if (P.split == 0) {
+          C += 0.5 * (d1(qu, d, i, j, k) + u[d] * d1(Qf(f), d, i, j, k) +
+                      cons(f, i, j, k) * d1(U(d), d, i, j, k));
+          continue;
+        }
+        // the seven terms of the whole-field residual, at this point
+        auto Ph = [&, f](int x, int y, int z) { return phi(f, x, y, z); };
+        auto uph = [&, f, d](int x, int y, int z) { return vel(d, x, y, z) * phi(f, x, y, z); };
+        const double ph0 = phi(f, i, j, k);
+        const double t_div = d1(qu, d, i, j, k);
+        const double t_uDq = u[d] * d1(Qf(f), d, i, j, k);
+        const double t_qDu = cons(f, i, j, k) * d1(U(d), d, i, j, k);
+        const double t_phDm = ph0 * d1(Qf(d + 1), d, i, j, k);
+        const double t_mDph = cons(d + 1, i, j, k) * d1(Ph, d, i, j, k);
+        const double t_rDuf = cons(0, i, j, k) * d1(uph, d, i, j, k);
+        const double t_ufDr = u[d] * ph0 * d1(Qf(0), d, i, j, k);
+        if (P.split == 1)
+          C += t_div;
+        else if (P.split == 2)
+          C += 0.5 * (t_div + t_phDm + t_mDph);
+        else if (P.split == 3)
+          C += 0.5 * (t_div + t_rDuf + t_ufDr);
+        else
+          C += 0.25 * (t_div + t_rDuf + t_uDq + t_phDm + t_mDph + t_qDu + t_ufDr);
       }
       out[f] -= C;
     }

@@ -101,3 +101,66 @@ def test_split_forms_inviscid_trajectory_matches_oracle():
         for f in range(5):
             rel = np.linalg.norm(q[f] - q_ref[f]) / np.linalg.norm(q_ref[f])
             assert rel <= 1e-12, (name, f, rel)
+
+
+@pytest.fixture(scope="module")
+def tgv512():
+    """Taylor-Green state at 512^3 with the symmetry mildly broken (FP64)."""
+    n = 512
+    q64 = O.init(oracle_params(tgv.Params(n=(n, n, n))))
+    q64[1:4] *= 1.0 + 0.01 * np.cos(np.arange(n))[None, None, None, :]
+    return q64
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+@pytest.mark.parametrize("form", ["DP", "HPSP"])
+def test_split_fused_stage_full_size_sampled(name, split, form, tgv512):
+    """The benchmark's split-form leg: one fused stage (stage 2 of 3) at 512^3
+    in the DP and HPSP forms, compared at 2000 sampled points (plus corners)
+    with the oracle's pointwise residual of the same split form combined by the
+    stage formula: FP64 within 1e-12 of the term scale, HPSP within the
+    rounding bound of its arithmetic and storage types."""
+    say("split fused full size sampled", name, form)
+    n = 512
+    prec = tgv.PRESETS[form]
+    p = tgv.Params(n=(n, n, n), split=split)
+    po = oracle_params(p)
+    qs = rounded(tgv512, prec.q)
+    qw = widened(qs)
+    rng = np.random.default_rng(n + 10 + split)
+    idx = np.unique(np.concatenate([rng.choice(p.N, 2000, replace=False),
+                                    [0, n - 1, n * n - 1, n * n * (n - 1), p.N - 1]])).astype(np.int64)
+    R = O.residual_at(po, qw, idx)
+    q_s = qw.reshape(5, -1)[:, idx].T.copy()
+    del qw
+    qt_s = 0.5 * q_s  # the register is Q / 2 (exact in every storage type here)
+    q = qs.to(DEV)
+    del qs
+    qt = (q * 0.5).to(prec.qt)
+    q_out = torch.empty_like(q)
+    stage, dt = 1, 2.3125e-4
+    tgv.ns_residual_rk_stage(p, prec, stage, dt, q, q_out, qt)
+    ti = torch.from_numpy(idx).to(DEV)
+    got_qt = widened(qt.reshape(5, -1)[:, ti].T)
+    got_q = widened(q_out.reshape(5, -1)[:, ti].T)
+    del q, qt, q_out
+    torch.cuda.empty_cache()
+    A, B = O.RK_A[stage], O.RK_B[stage]
+    ref_qt = A * qt_s + dt * R
+    ref_q = q_s + B * ref_qt
+    # field magnitudes of the Taylor-Green state (read off a 16^3 copy), spacing of this grid
+    scale = term_scale(p.n, p.L, p.gamma, O.init(oracle_params(tgv.Params(n=(16, 16, 16)))))
+    if form == "DP":
+        u = UNIT_ROUNDOFF[torch.float64]
+        tol_qt = 4 * u * (np.abs(A * qt_s) + dt * np.abs(R)) + dt * 1e-12 * scale[None, :]
+        tol_q = 4 * u * (np.abs(q_s) + np.abs(B * ref_qt)) + B * tol_qt
+    else:
+        uc, ur = UNIT_ROUNDOFF[prec.compute], UNIT_ROUNDOFF[prec.r]
+        ua = 2.0 ** -24
+        ut, uq = UNIT_ROUNDOFF[prec.qt], UNIT_ROUNDOFF[prec.q]
+        tol_R = 64 * uc * scale[None, :] + 2 * ur * np.abs(R)
+        tol_qt = dt * tol_R + 2 * ua * (np.abs(A * qt_s) + dt * np.abs(R)) + ut * np.abs(ref_qt)
+        tol_q = B * tol_qt + 2 * ua * (np.abs(q_s) + abs(B) * np.abs(ref_qt)) + uq * np.abs(ref_q)
+    say("  max err / tol", np.max(np.abs(got_qt - ref_qt) / tol_qt), np.max(np.abs(got_q - ref_q) / tol_q))
+    assert np.all(np.abs(got_qt - ref_qt) <= tol_qt)
+    assert np.all(np.abs(got_q - ref_q) <= tol_q)

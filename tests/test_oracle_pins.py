@@ -335,8 +335,12 @@ def test_split_forms_relations():
         assert np.abs(R[a][1] - R[b][1]).max() > 1e-4 * np.abs(R[b][1]).max(), (a, b)
 
 
-def test_residual_pointwise_matches_whole_field():
-    p = P((12, 16, 20))
+@pytest.mark.parametrize("split", sorted(O.SPLIT_FORMS.values()))
+def test_residual_pointwise_matches_whole_field(split):
+    """The pointwise evaluator (used for sampled checks on full-size grids) is a
+    second, independent transcription of the residual: every split form agrees
+    with the whole-field oracle, which is pinned by the tests above."""
+    p = P((12, 16, 20), split=split)
     q = S.random_state(p.n, 5)
     r = O.residual(p, q)
     idx = np.random.default_rng(0).choice(p.N, 300, replace=False)
