@@ -50,8 +50,9 @@ namespace {
 
 constexpr int TX = 64, TY = 8, NT = TX * TY;
 // A 512-thread block is two waves on each of the CU's four SIMDs, so every
-// instance has at most 256 VGPRs per lane; the FP64 fused instances spill a
-// few registers at that limit, the FP32 ones fit with room to spare.
+// instance has at most 256 VGPRs per lane; of the instances that run this
+// kernel, only the fused one with FP64 arithmetic on FP32 storage spills (a
+// few registers).
 template <class Tc>
 constexpr int kWavesPerEU = 2;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
