@@ -682,7 +682,7 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   if (FUSED && emit && col_valid && !rk.first) {
     const long long id = (long long)k * g.plane + col_off;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qt_k[f] = rk.qt[f * g.N + id];
+    for (int f = 0; f < 5; ++f) qt_k[f] = stream_load(&rk.qt[f * g.N + id]);
   }
   // 1. primitives of plane p + 1 into the other buffer; loads of plane p + 2
   if (p + 1 <= p_last) {

@@ -119,6 +119,16 @@ __device__ __forceinline__ void stream_store(T* p, T v) {
     *p = v;
 }
 
+// Load with the nontemporal hint: for inputs each point reads once (the RK
+// register Q~), unlike Q, whose halo rows neighbouring tiles re-read from L2.
+template <class T>
+__device__ __forceinline__ T stream_load(const T* p) {
+  if constexpr (std::is_arithmetic<T>::value || std::is_same<T, _Float16>::value)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 template <class T, class Tc>
 __device__ __forceinline__ T store_as(Tc x) {
   return Conv<T>::from(x);
