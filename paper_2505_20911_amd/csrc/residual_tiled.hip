@@ -884,8 +884,8 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
                         hipStream_t st) {
   // Kernel choice (measured at 512^3 and 1024^3): the warp-specialised
   // kernel, on 32 x 8 tiles for FP64 arithmetic (256 columns per role, as
-  // many as the registers allow; narrower than 64 so that fewer halo rows
-  // are loaded per point) and 64 x 8 tiles for FP32 arithmetic; the
+  // many as the registers allow; a 36 x 12 plane has fewer halo points to
+  // load and convert than 68 x 8) and 64 x 8 tiles for FP32 arithmetic; the
   // single-role kernel for two forms where it is faster: the fused stage
   // with FP64 Q and FP32 arithmetic (its Q_in ring does not fit the z role's
   // registers) and FP32 Q with FP64 arithmetic.
