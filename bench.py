@@ -348,8 +348,8 @@ def cpu_baseline(n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU slab "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the slab decomposition over "
+              "several GPUs is a design, not implemented", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)

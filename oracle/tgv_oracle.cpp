@@ -3,7 +3,7 @@
 // A plain, slow, deliberately unoptimised implementation of what the explicit
 // finite-difference time step of the compressible Navier-Stokes equations for
 // the Taylor-Green vortex computes (paper: Sec. 2.3.1, Sec. 3.1, Sec. 4.1).
-// Only the tests, the graft smoke check and the CPU-baseline leg of the
+// Only the tests, __graft_entry__.smoke() and the CPU-baseline leg of the
 // benchmark may load it.  It shares no code, header or constant with the GPU
 // library; the product path never calls it.
 //
