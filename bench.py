@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint kernels and gradient timing")
     ap.add_argument("--no-splits", action="store_true", help="skip the timing of the other split forms")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="time the adjoint kernels but not the 128^3 gradient workload (for profiling runs)")
     ap.add_argument("--cpu-n", type=int, default=256, help="grid of the oracle sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 launches), to calibrate the "
@@ -221,7 +223,7 @@ def time_form(form, n, steps, warmup, dt, fused):
     return out
 
 
-def adjoint_leg(n, form="DP", launches=5):
+def adjoint_leg(n, form="DP", launches=5, gradient=True):
     """Average duration and algorithmic bandwidth of the three adjoint entry
     points on an n^3 grid (one warm-up launch each, then `launches` timed with
     HIP events on the launch stream), and the wall time of the 128^3 gradient
@@ -263,6 +265,8 @@ def adjoint_leg(n, form="DP", launches=5):
                                 "frac_hbm": algo / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del q, rbar, qbar, zeta, aw, ew
     torch.cuda.empty_cache()
+    if not gradient:
+        return out
     # the gradient workload of the differentiation form
     grad = {}
     for gform in ("DP", "SP"):
@@ -408,11 +412,11 @@ def main():
     }
     if not args.no_adjoint:
         print(f"[bench] adjoint kernels at {n}^3 and the 128^3 gradient workload", file=sys.stderr, flush=True)
-        line["adjoint"] = adjoint_leg(n)
+        line["adjoint"] = adjoint_leg(n, gradient=not args.no_gradient)
         ak = line["adjoint"]["kernels"]
         print("[bench] adjoint: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['gbs']:.0f} GB/s" for k, v in ak.items())
               + "; gradient " + ", ".join(f"{k} {v['wall_s']:.2f} s" for k, v in
-                                          line["adjoint"]["gradient_128_400steps_20slots"].items()),
+                                          line["adjoint"].get("gradient_128_400steps_20slots", {}).items()),
               file=sys.stderr, flush=True)
     if not args.no_splits:
         print(f"[bench] split forms at {n}^3 (DP, HPSP)", file=sys.stderr, flush=True)
