@@ -898,8 +898,8 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   // Planes per block: long z-marches amortise the 4 halo planes a block
   // loads at its ends, but the grid must still hold enough blocks to fill
   // the chip several times over.
-  int kz = 256;
-  while (kz > 16 && (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz) < 2048) kz /= 2;
+  int kz = 512;
+  while (kz > 16 && (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz) < 1024) kz /= 2;
   const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
