@@ -572,18 +572,31 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 //             combinations of plane p - 1 from the ring, and the emission of
 //             plane p - 3 (z terms, z-mixed terms, store or RK stage).
 // One barrier per step (double-buffered plane).
-template <int WTX, int WTY>
+// The z role loads the plane in runs of V consecutive x-points per lane (one
+// V-element load per field): V = 2 halves the load instructions of the halo
+// plane.  A run never crosses the periodic wrap in x and is V-element aligned
+// when nx is even (tile origins and the halo width are even); odd nx takes
+// V = 1.
+template <int WTX, int WTY, int V = 1>
 struct Ws {
   static constexpr int TX = WTX, HX = WTX + 4, TY = WTY, NCOL = WTX * WTY, NT = 2 * NCOL, HY = WTY + 4,
                        NPL = HX * HY;
-  static constexpr int LOADS = (NPL + NCOL - 1) / NCOL;
+  static_assert(HX % V == 0, "a load run must not cross a halo row");
+  static constexpr int VPR = HX / V, NVS = NPL / V;  // runs per halo row and per plane
+  static constexpr int LOADS = (NVS + NCOL - 1) / NCOL;
 };
 #define TGV_WS_DIMS                                                                          \
   constexpr int WS_TX = Ws<WTX, WTY>::TX, WS_HX = Ws<WTX, WTY>::HX, WS_TY = Ws<WTX, WTY>::TY;     \
   constexpr int WS_NCOL = Ws<WTX, WTY>::NCOL, WS_NPL = Ws<WTX, WTY>::NPL;                 \
-  constexpr int WS_LOADS = Ws<WTX, WTY>::LOADS;                                            \
-  (void)WS_TY;                                                                               \
-  (void)WS_LOADS;
+  (void)WS_TY;
+#define TGV_WS_RUNS                                                                          \
+  constexpr int WS_VPR = Ws<WTX, WTY, V>::VPR, WS_NVS = Ws<WTX, WTY, V>::NVS;              \
+  constexpr int WS_LOADS = Ws<WTX, WTY, V>::LOADS;
+
+template <class T, int V>
+struct alignas(sizeof(T) * V) Run {
+  T e[V];
+};
 
 // The warp-specialised kernel keeps the reduced window (conserved variables
 // and 1/rho) in every precision: its z role has half the registers.
@@ -666,13 +679,15 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
   for (int a = 0; a < 3; ++a) ring_a[a * WS_NCOL + col] = A3[a];
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int PH>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int V, int PH>
 __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, ZCtx<Tc>& zc,
                                        QRing6<Tq>& qr, const Tc* cur, Tc* next, const Tc* ring_r,
-                                       const Tc* ring_a_prev, bool have_prev, Tc (&nxt)[Ws<WTX, WTY>::LOADS][5],
-                                       const long long (&off)[Ws<WTX, WTY>::LOADS], int p, int z0, int z1, int p_last,
-                                       bool col_valid, long long col_off, int zt) {
+                                       const Tc* ring_a_prev, bool have_prev,
+                                       Tc (&nxt)[Ws<WTX, WTY, V>::LOADS][V][5],
+                                       const long long (&off)[Ws<WTX, WTY, V>::LOADS], int p, int z0, int z1,
+                                       int p_last, bool col_valid, long long col_off, int zt) {
   TGV_WS_DIMS
+  TGV_WS_RUNS
   constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   const Grid& g = K.g;
   const Coef<Tc>& c = K.c;
@@ -688,12 +703,16 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   if (p + 1 <= p_last) {
 #pragma unroll
     for (int l = 0; l < WS_LOADS; ++l) {
-      const int s = zt + l * WS_NCOL;
-      if (s < WS_NPL) {
-        Tc f[NF];
-        primitives(nxt[l], f, c);
+      const int sv = zt + l * WS_NCOL;
+      if (sv < WS_NVS) {
+        const int s0 = (sv / WS_VPR) * WS_HX + (sv % WS_VPR) * V;
 #pragma unroll
-        for (int m = 0; m < NF; ++m) next[m * WS_NPL + s] = f[m];
+        for (int e = 0; e < V; ++e) {
+          Tc f[NF];
+          primitives(nxt[l][e], f, c);
+#pragma unroll
+          for (int m = 0; m < NF; ++m) next[m * WS_NPL + s0 + e] = f[m];
+        }
       }
     }
     if (p + 2 <= p_last) {
@@ -703,10 +722,14 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
       const long long zo = (long long)z * g.plane;
 #pragma unroll
       for (int l = 0; l < WS_LOADS; ++l) {
-        const int s = zt + l * WS_NCOL;
-        if (s < WS_NPL) {
+        const int sv = zt + l * WS_NCOL;
+        if (sv < WS_NVS) {
 #pragma unroll
-          for (int f = 0; f < 5; ++f) nxt[l][f] = load_as<Tc>(K.q[f * g.N + zo + off[l]]);
+          for (int f = 0; f < 5; ++f) {
+            const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
+#pragma unroll
+            for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+          }
         }
       }
     }
@@ -782,10 +805,11 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   }
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int V>
 __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
                                                                       int tiles_x, int tiles_y, int kz, int remap) {
   TGV_WS_DIMS
+  TGV_WS_RUNS
   __shared__ Tc lds[2][NF * WS_NPL];
   __shared__ Tc ring_r[RR_SLOTS][5 * WS_NCOL];
   __shared__ Tc ring_a[RA_SLOTS][3 * WS_NCOL];
@@ -805,8 +829,8 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
   long long off[WS_LOADS];
 #pragma unroll
   for (int l = 0; l < WS_LOADS; ++l) {
-    const int s = col + l * WS_NCOL;
-    const int lx = s % WS_HX, ly = s / WS_HX;
+    const int sv = col + l * WS_NCOL;
+    const int lx = (sv % WS_VPR) * V, ly = sv / WS_VPR;
     int x = (x0 - 2 + lx) % g.nx;
     x += (x < 0) ? g.nx : 0;
     int y = (y0 - 2 + ly) % g.ny;
@@ -817,7 +841,7 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
   const bool col_valid = cxg < g.nx && cyg < g.ny;
   const long long col_off = (long long)cyg * g.nx + cxg;
   const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
-  Tc nxt[WS_LOADS][5];
+  Tc nxt[WS_LOADS][V][5];
   if (zrole) {
     // plane p_first into buffer 0, plane p_first + 1 into registers
     for (int h = 0; h < 2; ++h) {
@@ -827,19 +851,28 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
       const long long zo = (long long)z * g.plane;
 #pragma unroll
       for (int l = 0; l < WS_LOADS; ++l) {
-        const int s = col + l * WS_NCOL;
+        const int sv = col + l * WS_NCOL;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) nxt[l][f] = s < WS_NPL ? load_as<Tc>(K.q[f * g.N + zo + off[l]]) : Tc(1);
+        for (int f = 0; f < 5; ++f) {
+          Run<Tq, V> v;
+          if (sv < WS_NVS) v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
+#pragma unroll
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = sv < WS_NVS ? load_as<Tc>(v.e[e]) : Tc(1);
+        }
       }
       if (h == 0) {
 #pragma unroll
         for (int l = 0; l < WS_LOADS; ++l) {
-          const int s = col + l * WS_NCOL;
-          if (s < WS_NPL) {
-            Tc f[NF];
-            primitives(nxt[l], f, K.c);
+          const int sv = col + l * WS_NCOL;
+          if (sv < WS_NVS) {
+            const int s0 = (sv / WS_VPR) * WS_HX + (sv % WS_VPR) * V;
 #pragma unroll
-            for (int m = 0; m < NF; ++m) lds[0][m * WS_NPL + s] = f[m];
+            for (int e = 0; e < V; ++e) {
+              Tc f[NF];
+              primitives(nxt[l][e], f, K.c);
+#pragma unroll
+              for (int m = 0; m < NF; ++m) lds[0][m * WS_NPL + s0 + e] = f[m];
+            }
           }
         }
       }
@@ -855,7 +888,7 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
     if (!zrole) {                                                                                                \
       if (pp <= p_last) ip_step<Tc, SPLIT, WTX, WTY>(K.c, lds[tt % 2], ring_r[tt % RR_SLOTS], ring_a[tt % RA_SLOTS], col); \
     } else {                                                                                                     \
-      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, WTX, WTY, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
+      z_step<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, WTX, WTY, V, PH>(K, rk, zc, qr, lds[tt % 2], lds[(tt + 1) % 2],              \
                                                     ring_r[(tt + 1) % RR_SLOTS], ring_a[(tt + 1) % RA_SLOTS],    \
                                                     tt >= 1, nxt, off, pp, z0, z1, p_last, col_valid, col_off, col); \
     }                                                                                                            \
@@ -903,10 +936,18 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
-  if constexpr (kWs)
-    hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty>), dim3((unsigned)nb),
-                       dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
-  else
+  if constexpr (kWs) {
+    // Paired halo loads (V = 2) for FP64 arithmetic only: the fused stage
+    // gains 1-4 % (bitwise the same results); the FP32-arithmetic instances
+    // run 2-12 % slower with them (a few spilled registers) and keep V = 1.
+    constexpr bool kPairs = sizeof(Tc) == 8;
+    if (kPairs && g.nx % 2 == 0)
+      hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty, kPairs ? 2 : 1>),
+                         dim3((unsigned)nb), dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
+    else
+      hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty, 1>), dim3((unsigned)nb),
+                         dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
+  } else
     hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K,
                        rk, tiles_x, tiles_y, kz, remap);
   return hipGetLastError();
