@@ -17,7 +17,7 @@ from tgv_testutil import UNIT_ROUNDOFF, oracle_params, rounded, term_scale, wide
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
-GRIDS = [(16, 16, 16), (32, 32, 32), (24, 32, 40), (5, 6, 7), (70, 20, 37), (128, 16, 64)]
+GRIDS = [(16, 16, 16), (32, 32, 32), (24, 32, 40), (5, 6, 7), (70, 20, 37), (69, 20, 37), (128, 16, 64)]
 
 
 def say(*a):
@@ -174,7 +174,7 @@ def test_rk_stage_matches_oracle(form, stage):
 
 # ---------------------------------------------------------------- fused residual + RK stage
 @pytest.mark.parametrize("form", ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"])
-@pytest.mark.parametrize("n", [(24, 32, 40), (5, 6, 7), (64, 8, 70)])
+@pytest.mark.parametrize("n", [(24, 32, 40), (5, 6, 7), (64, 8, 70), (69, 20, 37)])
 def test_fused_stage_equals_residual_then_stage(form, n):
     """ns_residual_rk_stage is the same computation as ns_residual followed by
     rk_stage (R rounded to its storage type in both): bitwise equal."""
