@@ -57,6 +57,17 @@ template <class Tc>
 constexpr int kWavesPerEU = 2;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
+// Plane loads in runs of V consecutive x-points per lane (V = 2 when nx is
+// even: a run then never crosses the periodic wrap and is V-element aligned).
+template <int V>
+struct Sr {
+  static_assert(HX % V == 0, "a load run must not cross a halo row");
+  static constexpr int VPR = HX / V, NVS = NPL / V, LOADS = (NVS + NT - 1) / NT;
+};
+template <class T, int V>
+struct alignas(sizeof(T) * V) Run {
+  T e[V];
+};
 constexpr int NF = 10;
 enum { F_RHO = 0, F_M = 1, F_E = 4, F_U = 5, F_P = 8, F_T = 9 };
 
@@ -311,12 +322,13 @@ struct RkArgs {
 };
 
 // One z-step with the newest plane in window slot PH.
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int PH>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int V, int PH>
 __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, Ctx<Tc>& cx,
                                       QRing<Tq>& qr,
-                                      Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k, Tc (&nxt)[LOADS][5],
-                                      const long long (&off)[LOADS], int p, int kout_lo, int kout_hi,
-                                      bool col_valid, long long col_off, int p_last) {
+                                      Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k,
+                                      Tc (&nxt)[Sr<V>::LOADS][V][5], const long long (&off)[Sr<V>::LOADS], int p,
+                                      int kout_lo, int kout_hi, bool col_valid, long long col_off, int p_last) {
+  constexpr int VPR = Sr<V>::VPR, NVS = Sr<V>::NVS, VLOADS = Sr<V>::LOADS;
   // the window holds Q converted exactly to Tc when Tc is at least as wide as Tq
   constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   const int tid = threadIdx.x;
@@ -333,13 +345,17 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   }
   // 1. primitives of the prefetched plane into LDS
 #pragma unroll
-  for (int l = 0; l < LOADS; ++l) {
-    const int s = tid + l * NT;
-    if (s < NPL) {
-      Tc f[NF];
-      primitives(nxt[l], f, c);
+  for (int l = 0; l < VLOADS; ++l) {
+    const int sv = tid + l * NT;
+    if (sv < NVS) {
+      const int s0 = (sv / VPR) * HX + (sv % VPR) * V;
 #pragma unroll
-      for (int k = 0; k < NF; ++k) lds[k * NPL + s] = f[k];
+      for (int e = 0; e < V; ++e) {
+        Tc f[NF];
+        primitives(nxt[l][e], f, c);
+#pragma unroll
+        for (int k = 0; k < NF; ++k) lds[k * NPL + s0 + e] = f[k];
+      }
     }
   }
   __syncthreads();
@@ -355,11 +371,15 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
     z -= (z >= g.nz) ? g.nz : 0;
     const long long zo = (long long)z * g.plane;
 #pragma unroll
-    for (int l = 0; l < LOADS; ++l) {
-      const int s = tid + l * NT;
-      if (s < NPL) {
+    for (int l = 0; l < VLOADS; ++l) {
+      const int sv = tid + l * NT;
+      if (sv < NVS) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) nxt[l][f] = load_as<Tc>(K.q[f * g.N + zo + off[l]]);
+        for (int f = 0; f < 5; ++f) {
+          const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
+#pragma unroll
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+        }
       }
     }
   }
@@ -483,9 +503,10 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   __syncthreads();
 }
 
-template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
+template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int V>
 __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
                                                      int tiles_y, int kz, int remap) {
+  constexpr int VPR = Sr<V>::VPR, NVS = Sr<V>::NVS, VLOADS = Sr<V>::LOADS;
   __shared__ Tc lds[NF * NPL];
   __shared__ Tc lds_ri[RI_SLOTS * 5 * NT];
   const Grid& g = K.g;
@@ -506,11 +527,11 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 
   const int tid = threadIdx.x;
   // wrapped (x, y) offsets of the plane points this thread loads (fixed over z)
-  long long off[LOADS];
+  long long off[VLOADS];
 #pragma unroll
-  for (int l = 0; l < LOADS; ++l) {
-    const int s = tid + l * NT;
-    const int lx = s % HX, ly = s / HX;
+  for (int l = 0; l < VLOADS; ++l) {
+    const int sv = tid + l * NT;
+    const int lx = (sv % VPR) * V, ly = sv / VPR;
     int x = (x0 - 2 + lx) % g.nx;
     x += (x < 0) ? g.nx : 0;
     int y = (y0 - 2 + ly) % g.ny;
@@ -522,21 +543,25 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   const long long col_off = (long long)cyg * g.nx + cxg;
 
   // prefetch the first plane
-  Tc nxt[LOADS][5];
+  Tc nxt[VLOADS][V][5];
   {
     int z = z0 - 2;
     z += (z < 0) ? g.nz : 0;
     z -= (z >= g.nz) ? g.nz : 0;
     const long long zo = (long long)z * g.plane;
 #pragma unroll
-    for (int l = 0; l < LOADS; ++l) {
-      const int s = tid + l * NT;
-      if (s < NPL) {
+    for (int l = 0; l < VLOADS; ++l) {
+      const int sv = tid + l * NT;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) nxt[l][f] = load_as<Tc>(K.q[f * g.N + zo + off[l]]);
-      } else {
+      for (int f = 0; f < 5; ++f) {
+        if (sv < NVS) {
+          const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) nxt[l][f] = Tc(1);
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = Tc(1);
+        }
       }
     }
   }
@@ -546,15 +571,15 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   // plane p = p_first + t sits in RI slot t % 3; the plane emitted with it,
   // p - 2, in slot (t - 2) % 3 = (t + 1) % 3.
   for (int p = p_first, t = 0; p <= p_last; p += 5, t += 5) {
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 0>(K, rk, cx, qr, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, V, 0>(K, rk, cx, qr, lds, lds_ri, (t + 0) % RI_SLOTS, (t + 0 + 1) % RI_SLOTS, nxt, off, p, z0, z1, col_valid, col_off, p_last);
     if (p + 1 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 1>(K, rk, cx, qr, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, V, 1>(K, rk, cx, qr, lds, lds_ri, (t + 1) % RI_SLOTS, (t + 1 + 1) % RI_SLOTS, nxt, off, p + 1, z0, z1, col_valid, col_off, p_last);
     if (p + 2 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 2>(K, rk, cx, qr, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, V, 2>(K, rk, cx, qr, lds, lds_ri, (t + 2) % RI_SLOTS, (t + 2 + 1) % RI_SLOTS, nxt, off, p + 2, z0, z1, col_valid, col_off, p_last);
     if (p + 3 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 3>(K, rk, cx, qr, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, V, 3>(K, rk, cx, qr, lds, lds_ri, (t + 3) % RI_SLOTS, (t + 3 + 1) % RI_SLOTS, nxt, off, p + 3, z0, z1, col_valid, col_off, p_last);
     if (p + 4 > p_last) break;
-    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 4>(K, rk, cx, qr, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
+    zstep<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, V, 4>(K, rk, cx, qr, lds, lds_ri, (t + 4) % RI_SLOTS, (t + 4 + 1) % RI_SLOTS, nxt, off, p + 4, z0, z1, col_valid, col_off, p_last);
   }
 }
 
@@ -593,10 +618,6 @@ struct Ws {
   constexpr int WS_VPR = Ws<WTX, WTY, V>::VPR, WS_NVS = Ws<WTX, WTY, V>::NVS;              \
   constexpr int WS_LOADS = Ws<WTX, WTY, V>::LOADS;
 
-template <class T, int V>
-struct alignas(sizeof(T) * V) Run {
-  T e[V];
-};
 
 // The warp-specialised kernel keeps the reduced window (conserved variables
 // and 1/rho) in every precision: its z role has half the registers.
@@ -940,6 +961,8 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
     // Paired halo loads (V = 2) for FP64 arithmetic only: the fused stage
     // gains 1-4 % (bitwise the same results); the FP32-arithmetic instances
     // run 2-12 % slower with them (a few spilled registers) and keep V = 1.
+    // The single-role kernel below takes pairs in every form it runs (SPDP
+    // fused 2 %, SP_DPC 3.5 % faster).
     constexpr bool kPairs = sizeof(Tc) == 8;
     if (kPairs && g.nx % 2 == 0)
       hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty, kPairs ? 2 : 1>),
@@ -947,9 +970,14 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
     else
       hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty, 1>), dim3((unsigned)nb),
                          dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
-  } else
-    hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT>), dim3((unsigned)nb), dim3(NT), 0, st, K,
-                       rk, tiles_x, tiles_y, kz, remap);
+  } else {
+    if (g.nx % 2 == 0)
+      hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 2>), dim3((unsigned)nb), dim3(NT), 0, st,
+                         K, rk, tiles_x, tiles_y, kz, remap);
+    else
+      hipLaunchKernelGGL((residual_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, 1>), dim3((unsigned)nb), dim3(NT), 0, st,
+                         K, rk, tiles_x, tiles_y, kz, remap);
+  }
   return hipGetLastError();
 }
 
