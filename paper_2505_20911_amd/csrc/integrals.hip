@@ -22,7 +22,18 @@ namespace {
 
 constexpr int IX = 64, IY = 4, kThreads = IX * IY;
 constexpr int IHX = IX + 4, IHY = IY + 4, IPL = IHX * IHY;  // plane incl. halo
-constexpr int ILOADS = (IPL + kThreads - 1) / kThreads;
+// The plane is loaded in runs of consecutive x-points per lane (the RUN
+// parameter of pass 1): two when nx is even (tile origins and the halo width
+// are even, so a run never crosses the periodic wrap and stays aligned to its
+// length), else one.
+template <int V>
+struct IRuns {
+  static constexpr int VPR = IHX / V, NVS = IPL / V, LOADS = (NVS + kThreads - 1) / kThreads;
+};
+template <class T, int V>
+struct alignas(sizeof(T) * V) IRun {
+  T e[V];
+};
 
 struct IntLaunch {
   int tiles_x, tiles_y, kz;
@@ -60,10 +71,11 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i;
 }
 
-template <class Tq>
+template <class Tq, int RUN>
 __global__ void __launch_bounds__(kThreads) integrals_pass1(Grid g, Coef<double> c, const Tq* __restrict__ q,
                                                             double* __restrict__ work, int tiles_x, int tiles_y,
                                                             int kz) {
+  constexpr int VPR = IRuns<RUN>::VPR, NVS = IRuns<RUN>::NVS, ILOADS = IRuns<RUN>::LOADS;
   __shared__ double vel[2][3][IPL];  // double-buffered velocity plane
   __shared__ double red[4];
   // contiguous runs of tiles per XCD (hardware block b runs on XCD b % 8),
@@ -77,20 +89,23 @@ __global__ void __launch_bounds__(kThreads) integrals_pass1(Grid g, Coef<double>
   const int z1 = min(z0 + kz, g.nz);
   const int tid = threadIdx.x;
 
-  // plane slots this thread loads: wrapped offset within a plane, and
-  // whether the slot is one of the tile's own (interior, in-grid) points
+  // runs this thread loads: wrapped offset of the run's first point within
+  // a plane, and whether each point is one of the tile's own (interior,
+  // in-grid) points
   long long off[ILOADS];
-  bool own[ILOADS];
+  bool own[ILOADS][RUN];
 #pragma unroll
   for (int l = 0; l < ILOADS; ++l) {
-    const int s = tid + l * kThreads;
-    const int lx = s % IHX, ly = s / IHX;
+    const int sv = tid + l * kThreads;
+    const int lx = (sv % VPR) * RUN, ly = sv / VPR;
     int x = (x0 - 2 + lx) % g.nx, y = (y0 - 2 + ly) % g.ny;  // the halo may wrap more than once
     x += (x < 0) ? g.nx : 0;
     y += (y < 0) ? g.ny : 0;
     off[l] = (long long)y * g.nx + x;
-    own[l] = s < IPL && lx >= 2 && lx < IX + 2 && ly >= 2 && ly < IY + 2 && x0 - 2 + lx < g.nx &&
-             y0 - 2 + ly < g.ny;
+#pragma unroll
+    for (int e = 0; e < RUN; ++e)
+      own[l][e] = sv < NVS && lx + e >= 2 && lx + e < IX + 2 && ly >= 2 && ly < IY + 2 && x0 - 2 + lx + e < g.nx &&
+                  y0 - 2 + ly < g.ny;
   }
   const int tx = tid % IX, ty = tid / IX;
   const bool col_valid = x0 + tx < g.nx && y0 + ty < g.ny;
@@ -104,26 +119,34 @@ __global__ void __launch_bounds__(kThreads) integrals_pass1(Grid g, Coef<double>
     const bool inside = p >= z0 && p < z1;
 #pragma unroll
     for (int l = 0; l < ILOADS; ++l) {
-      const int s = tid + l * kThreads;
-      if (s < IPL) {
+      const int sv = tid + l * kThreads;
+      if (sv < NVS) {
         const long long id = zo + off[l];
-        const double rho = load_as<double>(q[id]);
-        const double m1 = load_as<double>(q[g.N + id]);
-        const double m2 = load_as<double>(q[2 * g.N + id]);
-        const double m3 = load_as<double>(q[3 * g.N + id]);
-        const double u = m1 / rho, v = m2 / rho, w = m3 / rho;
-        vel[buf][0][s] = u;
-        vel[buf][1][s] = v;
-        vel[buf][2][s] = w;
-        if (inside && own[l]) {
-          const double uu = u * u + v * v + w * w;
-          acc[0] += 0.5 * uu;
-          acc[1] += 0.5 * rho * uu;
-          acc[3] += rho;
-          acc[4] += m1;
-          acc[5] += m2;
-          acc[6] += m3;
-          acc[7] += load_as<double>(q[4 * g.N + id]);
+        const int s0 = (sv / VPR) * IHX + (sv % VPR) * RUN;
+        const IRun<Tq, RUN> rr = *reinterpret_cast<const IRun<Tq, RUN>*>(q + id);
+        const IRun<Tq, RUN> r1 = *reinterpret_cast<const IRun<Tq, RUN>*>(q + g.N + id);
+        const IRun<Tq, RUN> r2 = *reinterpret_cast<const IRun<Tq, RUN>*>(q + 2 * g.N + id);
+        const IRun<Tq, RUN> r3 = *reinterpret_cast<const IRun<Tq, RUN>*>(q + 3 * g.N + id);
+#pragma unroll
+        for (int e = 0; e < RUN; ++e) {
+          const double rho = load_as<double>(rr.e[e]);
+          const double m1 = load_as<double>(r1.e[e]);
+          const double m2 = load_as<double>(r2.e[e]);
+          const double m3 = load_as<double>(r3.e[e]);
+          const double u = m1 / rho, v = m2 / rho, w = m3 / rho;
+          vel[buf][0][s0 + e] = u;
+          vel[buf][1][s0 + e] = v;
+          vel[buf][2][s0 + e] = w;
+          if (inside && own[l][e]) {
+            const double uu = u * u + v * v + w * w;
+            acc[0] += 0.5 * uu;
+            acc[1] += 0.5 * rho * uu;
+            acc[3] += rho;
+            acc[4] += m1;
+            acc[5] += m2;
+            acc[6] += m3;
+            acc[7] += load_as<double>(q[4 * g.N + id + e]);
+          }
         }
       }
     }
@@ -188,8 +211,12 @@ template <class Tq>
 hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work, double* out8,
                             hipStream_t st) {
   const IntLaunch L = int_launch(g);
-  hipLaunchKernelGGL((integrals_pass1<Tq>), dim3((unsigned)L.blocks), dim3(kThreads), 0, st, g, c,
-                     static_cast<const Tq*>(q), work, L.tiles_x, L.tiles_y, L.kz);
+  if (g.nx % 2 == 0)
+    hipLaunchKernelGGL((integrals_pass1<Tq, 2>), dim3((unsigned)L.blocks), dim3(kThreads), 0, st, g, c,
+                       static_cast<const Tq*>(q), work, L.tiles_x, L.tiles_y, L.kz);
+  else
+    hipLaunchKernelGGL((integrals_pass1<Tq, 1>), dim3((unsigned)L.blocks), dim3(kThreads), 0, st, g, c,
+                       static_cast<const Tq*>(q), work, L.tiles_x, L.tiles_y, L.kz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(integrals_pass2, dim3(1), dim3(kThreads), 0, st, L.blocks, 1.0 / (double)g.N, c.ire, work,
