@@ -4,7 +4,8 @@
 //
 // Work decomposition.  A block of 64 x TY threads owns a 64 x TY tile of
 // (x, y) columns and marches along z over a chunk of planes.  Per plane p it
-//   1. loads Q on the tile plus a 2-point halo (coalesced along x), converts
+//   1. loads Q on the tile plus a 2-point halo (coalesced along x; two
+//      consecutive x-points per lane and field when nx is even), converts
 //      to the arithmetic type Tc and derives the primitive variables once per
 //      point into one LDS plane of 10 fields (rho, m1, m2, m3, rho E, u, v, w,
 //      p, T);
