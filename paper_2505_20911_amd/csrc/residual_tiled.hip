@@ -57,7 +57,6 @@ constexpr int TX = 64, TY = 8, NT = TX * TY;
 template <class Tc>
 constexpr int kWavesPerEU = 2;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
-constexpr int LOADS = (NPL + NT - 1) / NT;              // plane points per thread
 // Plane loads in runs of V consecutive x-points per lane (V = 2 when nx is
 // even: a run then never crosses the periodic wrap and is V-element aligned).
 template <int V>
