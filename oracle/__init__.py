@@ -59,9 +59,13 @@ def _load():
     for name, argt in sigs.items():
         fn = getattr(lib, name)
         fn.argtypes = argt
-        fn.restype = None
+        fn.restype = ctypes.c_int if name in _RETURNS_STATUS else None
     _lib = lib
     return lib
+
+
+# Entry points that return a status (0, or -1 when they refuse the split form).
+_RETURNS_STATUS = ("oracle_residual_adjoint", "oracle_dissipation_grad")
 
 
 def _p(a: np.ndarray):
@@ -73,8 +77,9 @@ def _p(a: np.ndarray):
 SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4}
 
 
-def _blaisdell_only(P, what):
-    if P.split != 0:
+def _blaisdell_only(status, what):
+    """The C routine refuses split forms other than Blaisdell (status -1)."""
+    if status != 0:
         raise ValueError(f"{what} is written for the Blaisdell split form only")
 
 
@@ -140,12 +145,12 @@ def residual_c(P: Params, q) -> np.ndarray:
 
 def residual_adjoint(P: Params, q, rbar, qbar=None) -> np.ndarray:
     """qbar += (dR/dQ)^T rbar (hand-written reverse mode of ``residual``)."""
-    _blaisdell_only(P, "residual_adjoint")
     q = _q(P, q)
     rbar = _q(P, rbar)
     if qbar is None:
         qbar = np.zeros_like(q)
-    _load().oracle_residual_adjoint(_p(P.packed()), _p(q), _p(rbar), _p(qbar))
+    _blaisdell_only(_load().oracle_residual_adjoint(_p(P.packed()), _p(q), _p(rbar), _p(qbar)),
+                    "residual_adjoint")
     return qbar
 
 
@@ -244,11 +249,11 @@ def dissipation_c(P: Params, dt: float, nsteps: int, q0) -> complex:
 
 def dissipation_grad(P: Params, dt: float, nsteps: int, q0):
     """(J, dJ/dQ^0) by store-all reverse mode through the RK3 stages."""
-    _blaisdell_only(P, "dissipation_grad")
     q0 = _q(P, q0)
     J = np.zeros(1, np.float64)
     g = np.zeros_like(q0)
-    _load().oracle_dissipation_grad(_p(P.packed()), float(dt), int(nsteps), _p(q0), _p(J), _p(g))
+    _blaisdell_only(_load().oracle_dissipation_grad(_p(P.packed()), float(dt), int(nsteps), _p(q0), _p(J), _p(g)),
+                    "dissipation_grad")
     return float(J[0]), g
 
 

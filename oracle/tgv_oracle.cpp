@@ -775,8 +775,13 @@ void oracle_residual_c(const double* pv, const cplx* q, cplx* r) {
   residual(unpack(pv), q, r);
 }
 
-void oracle_residual_adjoint(const double* pv, const double* q, const double* rbar, double* qbar) {
-  residual_adjoint(unpack(pv), q, rbar, qbar);
+// The adjoint is the transpose of the Blaisdell-split residual only: any
+// other split form is refused (return -1, qbar untouched).
+int oracle_residual_adjoint(const double* pv, const double* q, const double* rbar, double* qbar) {
+  const Params P = unpack(pv);
+  if (P.split != 0) return -1;
+  residual_adjoint(P, q, rbar, qbar);
+  return 0;
 }
 
 void oracle_rk_stage(int stage, double dt, long n5, double* q, double* qt, const double* r) {
@@ -894,9 +899,10 @@ void oracle_dissipation_c(const double* pv, double dt, int nsteps, cplx* q, cplx
 // Same J in double, plus its gradient with respect to the initial state Q^0
 // by store-all reverse mode over the RK3 stages (the reverse of
 // Qt^i = A_i Qt^{i-1} + dt R(Q^{i-1}),  Q^i = Q^{i-1} + B_i Qt^i).
-void oracle_dissipation_grad(const double* pv, double dt, int nsteps, const double* q0,
-                             double* J, double* qbar0) {
+int oracle_dissipation_grad(const double* pv, double dt, int nsteps, const double* q0,
+                            double* J, double* qbar0) {
   Params P = unpack(pv);
+  if (P.split != 0) return -1;  // reverse mode of the Blaisdell form only
   const long N = npts(P), n5 = 5 * N;
   // Stage inputs for every stage of every step.
   std::vector<std::vector<double>> Y((size_t)nsteps * 3 + 1, std::vector<double>());
@@ -935,6 +941,7 @@ void oracle_dissipation_grad(const double* pv, double dt, int nsteps, const doub
     }
   }
   std::memcpy(qbar0, qb.data(), n5 * sizeof(double));
+  return 0;
 }
 
 }  // extern "C"

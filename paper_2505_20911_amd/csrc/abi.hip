@@ -66,8 +66,10 @@ int check_params(const ns_params_t* p, tgv::Grid* g) {
     if (!finite_pos(p->L[d])) return fail(NS_ERR_ARG, "L[" + std::to_string(d) + "] must be finite and > 0");
   }
   const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
-  // Kernel grids use 32-bit block counts with 256 threads per block.
-  if (N > (1LL << 38)) return fail(NS_ERR_SHAPE, "grid has more than 2^38 points");
+  // Element-wise kernels loop grid-stride, so only the tiled kernels' block
+  // counts limit the grid (checked per entry point by check_launch); 2^34
+  // points exceed the device memory of any precision form.
+  if (N > (1LL << 34)) return fail(NS_ERR_SHAPE, "grid has more than 2^34 points");
   if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) return fail(NS_ERR_ARG, "gamma must be finite and > 1");
   if (!finite_pos(p->mach)) return fail(NS_ERR_ARG, "mach must be finite and > 0");
   if (p->viscous != 0 && p->viscous != 1) return fail(NS_ERR_ARG, "viscous must be 0 or 1");
@@ -97,6 +99,15 @@ int check_ptr(const void* ptr, const char* name) {
   if (!ptr) return fail(NS_ERR_ARG, std::string(name) + " is NULL");
   if (reinterpret_cast<uintptr_t>(ptr) % 16 != 0)
     return fail(NS_ERR_ALIGN, std::string(name) + " is not 16-byte aligned");
+  return NS_OK;
+}
+
+// A dispatch holds fewer than 2^32 work-items; grids whose tiled launch would
+// need more (very large, or extremely elongated) are refused before any HIP call.
+int check_launch(long long work_items, const char* what) {
+  if (work_items > (long long)0xffffffffu)
+    return fail(NS_ERR_SHAPE, std::string(what) + ": the grid needs " + std::to_string(work_items) +
+                                  " work-items in one dispatch (at most 2^32 - 1)");
   return NS_OK;
 }
 
@@ -176,6 +187,7 @@ int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q,
   if ((rc = check_prec(prec, &f)) || (rc = check_split(params, f))) return rc;
   if ((rc = check_ptr(q, "q")) || (rc = check_ptr(r, "r"))) return rc;
   if (q == r) return fail(NS_ERR_ARG, "q and r must not overlap");
+  if ((rc = check_launch(tgv::residual_work_items(g), "ns_residual"))) return rc;
   hipStream_t st = as_stream(stream);
   hipError_t e = hipSuccess;
   using tgv::bf16;
@@ -234,6 +246,7 @@ int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int s
   if (!std::isfinite(dt)) return fail(NS_ERR_ARG, "dt must be finite");
   if ((rc = check_ptr(q_in, "q_in")) || (rc = check_ptr(q_out, "q_out")) || (rc = check_ptr(qt, "qt"))) return rc;
   if (q_in == q_out || q_in == qt || q_out == qt) return fail(NS_ERR_ARG, "q_in, q_out and qt must be distinct arrays");
+  if ((rc = check_launch(tgv::residual_work_items(g), "ns_residual_rk_stage"))) return rc;
   hipStream_t st = as_stream(stream);
   hipError_t e = hipSuccess;
   using tgv::bf16;
@@ -291,6 +304,7 @@ int flow_integrals(const ns_params_t* params, const ns_prec_t* prec, const void*
   if ((rc = check_prec(prec, &f))) return rc;
   if ((rc = check_ptr(q, "q")) || (rc = check_ptr(workspace, "workspace")) || (rc = check_ptr(out8, "out8")))
     return rc;
+  if ((rc = check_launch(tgv::integrals_work_items(g), "flow_integrals"))) return rc;
   hipStream_t st = as_stream(stream);
   const tgv::Coef<double> c = make_coef<double>(params);
   hipError_t e;
@@ -344,6 +358,7 @@ int ns_residual_adjoint(const ns_params_t* params, const ns_prec_t* prec, const 
       (rc = check_ptr(workspace, "workspace")))
     return rc;
   if (q_bar == q || q_bar == r_bar) return fail(NS_ERR_ARG, "q_bar must not overlap q or r_bar");
+  if ((rc = check_launch(tgv::adjoint_work_items(g), "ns_residual_adjoint"))) return rc;
   hipStream_t st = as_stream(stream);
   hipError_t e = f64 ? tgv::launch_residual_adjoint<double>(g, make_coef<double>(params), q, r_bar, q_bar,
                                                            workspace, st)
@@ -386,6 +401,7 @@ int flow_integrals_adjoint(const ns_params_t* params, const ns_prec_t* prec, con
   if (!std::isfinite(eps_bar)) return fail(NS_ERR_ARG, "eps_bar must be finite");
   if ((rc = check_ptr(q, "q")) || (rc = check_ptr(q_bar, "q_bar")) || (rc = check_ptr(workspace, "workspace")))
     return rc;
+  if ((rc = check_launch(tgv::adjoint_work_items(g), "flow_integrals_adjoint"))) return rc;
   hipStream_t st = as_stream(stream);
   hipError_t e = f64 ? tgv::launch_integrals_adjoint<double>(g, make_coef<double>(params), q, eps_bar, q_bar,
                                                             workspace, st)

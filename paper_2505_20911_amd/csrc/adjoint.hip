@@ -116,9 +116,9 @@ static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 template <class T>
 __global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict__ q, const T* __restrict__ rb,
                                                      T* __restrict__ w) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
   const long long N = g.N;
+  for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < N;
+       id += (long long)gridDim.x * blockDim.x) {
   T q0[5], r0[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict
     const T u = q0[a + 1] * ir;
     w[(W_U + a) * N + id] = u;
     w[(W_VB + a) * N + id] = r0[a + 1] + r0[4] * u;
+  }
   }
 }
 
@@ -412,11 +413,12 @@ __global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef
 template <class T>
 __global__ void __launch_bounds__(kThreads) rk_adj(long long n5, T A, T B, T dt, const T* __restrict__ qbar,
                                                    T* __restrict__ zeta, T* __restrict__ rbar) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n5) return;
-  const T z = zeta[i] + B * qbar[i];
-  rbar[i] = dt * z;
-  zeta[i] = A * z;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n5;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T z = zeta[i] + B * qbar[i];
+    rbar[i] = dt * z;
+    zeta[i] = A * z;
+  }
 }
 
 // eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega.
@@ -481,9 +483,11 @@ __global__ void __launch_bounds__(kThreads) adj_curl(Grid g, ColMarch cm, Coef<T
   }
 }
 
-inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+inline unsigned blocks_for(long long n) { return blocks_1d(n, kThreads); }
 
 }  // namespace
+
+long long adjoint_work_items(const Grid& g) { return col_march(g).blocks * kThreads; }
 
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar, void* qbar,

@@ -11,8 +11,8 @@ namespace {
 template <class Tq>
 __global__ void __launch_bounds__(256) tgv_init_kernel(Grid g, double hx, double hy, double hz,
                                                        double gamma, double gm2, Tq* __restrict__ q) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.N) return;
+  for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < g.N;
+       id += (long long)gridDim.x * blockDim.x) {
   const int i = (int)(id % g.nx);
   const int j = (int)((id / g.nx) % g.ny);
   const int k = (int)(id / g.plane);
@@ -27,6 +27,7 @@ __global__ void __launch_bounds__(256) tgv_init_kernel(Grid g, double hx, double
   q[2 * g.N + id] = store_as<Tq>(rho * v);
   q[3 * g.N + id] = store_as<Tq>(0.0);
   q[4 * g.N + id] = store_as<Tq>(p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v));
+  }
 }
 
 }  // namespace
@@ -35,8 +36,7 @@ template <class Tq>
 hipError_t launch_init(const Grid& g, const double L[3], double gamma, double mach, void* q,
                        hipStream_t st) {
   const int threads = 256;
-  const long long blocks = (g.N + threads - 1) / threads;
-  hipLaunchKernelGGL((tgv_init_kernel<Tq>), dim3((unsigned)blocks), dim3(threads), 0, st, g, L[0] / g.nx,
+  hipLaunchKernelGGL((tgv_init_kernel<Tq>), dim3(blocks_1d(g.N, threads)), dim3(threads), 0, st, g, L[0] / g.nx,
                      L[1] / g.ny, L[2] / g.nz, gamma, gamma * mach * mach, static_cast<Tq*>(q));
   return hipGetLastError();
 }

@@ -207,6 +207,8 @@ __global__ void __launch_bounds__(kThreads) integrals_pass2(long long rows, doub
 
 long long integrals_blocks(const Grid& g) { return int_launch(g).blocks; }
 
+long long integrals_work_items(const Grid& g) { return int_launch(g).blocks * kThreads; }
+
 template <class Tq>
 hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work, double* out8,
                             hipStream_t st) {

@@ -931,7 +931,34 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
 #undef TGV_WS_STEP
 }
 
+struct TileLaunch {
+  int tiles_x, tiles_y, kz;
+  long long blocks;
+};
+
+// Planes per block: long z-marches amortise the 4 halo planes a block loads
+// at its ends, but the grid must still hold enough blocks to fill the chip
+// several times over.
+TileLaunch tile_launch(const Grid& g, int tx, int ty) {
+  TileLaunch L;
+  L.tiles_x = (g.nx + tx - 1) / tx;
+  L.tiles_y = (g.ny + ty - 1) / ty;
+  L.kz = 512;
+  while (L.kz > 16 && (long long)L.tiles_x * L.tiles_y * ((g.nz + L.kz - 1) / L.kz) < 1024) L.kz /= 2;
+  L.blocks = (long long)L.tiles_x * L.tiles_y * ((g.nz + L.kz - 1) / L.kz);
+  return L;
+}
+
 }  // namespace
+
+long long residual_work_items(const Grid& g) {
+  // the three launch geometries: warp-specialised 32 x 8 (512 threads) and
+  // 64 x 8 (1024 threads), single-role 64 x 8 (512 threads)
+  const long long a = tile_launch(g, 32, 8).blocks * Ws<32, 8>::NT;
+  const long long b = tile_launch(g, 64, 8).blocks * Ws<64, 8>::NT;
+  const long long c = tile_launch(g, TX, TY).blocks * NT;
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
 hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r, const RkArgs<Tq, Tqt, Ta>& rk,
@@ -947,14 +974,9 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8) && !(sizeof(Tc) == 8 && sizeof(Tq) < 8);
   constexpr int kWtx = sizeof(Tc) == 8 ? 32 : 64, kWty = 8;
   constexpr int kTx = kWs ? kWtx : TX, kTy = kWs ? kWty : TY;
-  const int tiles_x = (g.nx + kTx - 1) / kTx;
-  const int tiles_y = (g.ny + kTy - 1) / kTy;
-  // Planes per block: long z-marches amortise the 4 halo planes a block
-  // loads at its ends, but the grid must still hold enough blocks to fill
-  // the chip several times over.
-  int kz = 512;
-  while (kz > 16 && (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz) < 1024) kz /= 2;
-  const long long nb = (long long)tiles_x * tiles_y * ((g.nz + kz - 1) / kz);
+  const TileLaunch L = tile_launch(g, kTx, kTy);
+  const int tiles_x = L.tiles_x, tiles_y = L.tiles_y, kz = L.kz;
+  const long long nb = L.blocks;
   const int remap = nb % 8 == 0 ? 1 : 0;
   Kernel<Tq, Tr, Tc> K{g, c, static_cast<const Tq*>(q), static_cast<Tr*>(r)};
   if constexpr (kWs) {

@@ -63,8 +63,9 @@ template <class Tq, class Tqt, class Tr, class Ta, bool kFirst>
 __global__ void __launch_bounds__(256) rk_stage_kernel(long long n5, Ta A, Ta B, Ta dt, Tq* __restrict__ q,
                                                        Tqt* __restrict__ qt, const Tr* __restrict__ r) {
   constexpr int kElems = kElemsOf<Tq>;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;; t += (long long)gridDim.x * blockDim.x) {
   const long long base = t * kElems;
+  if (base >= n5) break;
   if (base + kElems <= n5) {
     const Chunk<Tr, kElems> rv = nt_load(reinterpret_cast<const Chunk<Tr, kElems>*>(r) + t);
     Chunk<Tq, kElems> qv = nt_load(reinterpret_cast<const Chunk<Tq, kElems>*>(q) + t);
@@ -89,6 +90,7 @@ __global__ void __launch_bounds__(256) rk_stage_kernel(long long n5, Ta A, Ta B,
       q[e] = store_as<Tq>(rk_state<Ta>(B, load_as<Ta>(q[e]), load_as<Ta>(ts)));
     }
   }
+  }
 }
 
 }  // namespace
@@ -101,14 +103,13 @@ hipError_t launch_rk_stage(const Grid& g, int stage, double dt, void* q, void* q
   const long long n5 = 5 * g.N;
   const int threads = 256;
   constexpr int kElems = kElemsOf<Tq>;
-  const long long chunks = (n5 + kElems - 1) / kElems;
-  const long long blocks = (chunks + threads - 1) / threads;
+  const unsigned blocks = blocks_1d((n5 + kElems - 1) / kElems, threads);
   const Ta A = (Ta)kA[stage], B = (Ta)kB[stage], tdt = (Ta)dt;
   if (stage == 0)
-    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, true>), dim3((unsigned)blocks), dim3(threads), 0, st,
+    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, true>), dim3(blocks), dim3(threads), 0, st,
                        n5, A, B, tdt, static_cast<Tq*>(q), static_cast<Tqt*>(qt), static_cast<const Tr*>(r));
   else
-    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, false>), dim3((unsigned)blocks), dim3(threads), 0, st,
+    hipLaunchKernelGGL((rk_stage_kernel<Tq, Tqt, Tr, Ta, false>), dim3(blocks), dim3(threads), 0, st,
                        n5, A, B, tdt, static_cast<Tq*>(q), static_cast<Tqt*>(qt), static_cast<const Tr*>(r));
   return hipGetLastError();
 }

@@ -164,6 +164,16 @@ __device__ __forceinline__ float recip(float x) {
   return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
 }
 
+// One-dimensional launches: a dispatch holds fewer than 2^32 work-items, so
+// element-wise kernels loop grid-stride over their index range and their block
+// count is capped here (a single pass for every grid up to 1024^3 x 5 values
+// at 256 threads per block).
+inline unsigned blocks_1d(long long work, int threads) {
+  long long b = (work + threads - 1) / threads;
+  const long long cap = (long long)(0xffffffffu / (unsigned)threads);
+  return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
+}
+
 // Grid description passed to kernels by value.
 struct Grid {
   int nx, ny, nz;

@@ -8,6 +8,12 @@
 
 namespace tgv {
 
+// Work-items of the largest dispatch each tiled kernel family makes on grid g
+// (a dispatch must hold fewer than 2^32; the C-ABI refuses larger grids).
+long long residual_work_items(const Grid& g);
+long long integrals_work_items(const Grid& g);
+long long adjoint_work_items(const Grid& g);
+
 template <class Tq>
 hipError_t launch_init(const Grid& g, const double L[3], double gamma, double mach, void* q,
                        hipStream_t st);

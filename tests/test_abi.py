@@ -166,3 +166,25 @@ def test_stream_probe_library_loads_and_validates_on_the_host():
     assert lib.tgv_probe_stage_stream(64, 0, 8, a, b, c, None) == -1
     assert lib.tgv_probe_stage_stream(64, 16, 3, a, b, c, None) == -1
     assert lib.tgv_probe_stage_stream(64, 16, 8, None, b, c, None) == -1
+
+
+def test_grid_size_limits_are_validated_before_launch():
+    """N <= 2^34 is accepted by the parameter check (the element-wise kernels
+    loop grid-stride, so no 1-D dispatch limit applies); a tiled launch that
+    would need 2^32 or more work-items in one dispatch is refused with
+    NS_ERR_SHAPE before any HIP call (the pointers here are never touched)."""
+    lib = tgv.load()
+    prec = tgv.PRESETS["DP"]
+    big = tgv.Params(n=(4096, 4096, 1025))  # 2^34 + 2^24 points
+    assert _call_residual(big, prec) == NS_ERR_SHAPE
+    assert "2^34" in tgv.ns_last_error()
+    # 5 x 5 x 2^28: within 2^34 points, but the adjoint's column march would
+    # need 2^24 blocks of 256 threads
+    thin = tgv.Params(n=(5, 5, 1 << 28))
+    rc = lib.ns_residual_adjoint(ctypes.byref(thin.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
+                                 ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None)
+    assert rc == NS_ERR_SHAPE
+    assert "work-items" in tgv.ns_last_error()
+    rc = lib.flow_integrals_adjoint(ctypes.byref(thin.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
+                                    ctypes.c_double(1.0), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None)
+    assert rc == NS_ERR_SHAPE

@@ -61,6 +61,11 @@ def test_ic_discrete_invariants(n):
     assert abs(I[1] - 0.125) < 1e-15
     assert abs(I[3] - 1.0) < 1e-15
     gm2 = p.gamma * p.mach ** 2
+    # <rho E> = <p>/(gamma-1) + K_rho = p0/(gamma-1) + 1/8, and the mean
+    # momentum vanishes (every momentum component is odd under a reflection)
+    E0 = 1 / gm2 / (p.gamma - 1) + 0.125
+    assert abs(I[7] - E0) <= 4e-16 * E0
+    assert np.all(np.abs(I[4:7]) <= 1e-16)
     rho, m, E = q[0], q[1:4], q[4]
     pr = (p.gamma - 1) * (E - 0.5 * (m ** 2).sum(0) / rho)
     assert abs(pr.mean() - 1 / gm2) < 1e-12
@@ -70,6 +75,22 @@ def test_ic_discrete_invariants(n):
     z, y, x = np.meshgrid(*(np.arange(m_) * 2 * np.pi / m_ for m_ in (nz, ny, nx)), indexing="ij")
     expect = (kprime(1, p.h(0)) - kprime(1, p.h(1))) * np.cos(x) * np.cos(y) * np.cos(z)
     assert np.abs(div - expect).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [8, (12, 20, 16), 64])
+def test_ic_pointwise_evaluator(n):
+    """init_at (the pointwise initial state, used for sampled checks at sizes
+    where the whole field is not formed) equals init element by element, and
+    the hand-evaluated points of the golden fixture."""
+    p = P(n)
+    q = O.init(p).reshape(5, -1)
+    idx = np.random.default_rng(5).choice(p.N, min(p.N, 4096), replace=False)
+    got = O.init_at(p, idx)
+    assert np.array_equal(got, q[:, idx].T)
+    if n == 8:
+        rows = np.loadtxt(os.path.join(GOLDEN, "tgv_ic_special_points.txt"))
+        lin = [(int(r[2]) * 8 + int(r[1])) * 8 + int(r[0]) for r in rows]
+        np.testing.assert_allclose(O.init_at(p, lin), rows[:, 3:], rtol=1e-14, atol=1e-14)
 
 
 @pytest.mark.parametrize("n", [8, 16, 32])
@@ -632,3 +653,19 @@ def test_trajectory_gradient_matches_complex_step():
     assert abs(Jc.real - J) <= 1e-14 * abs(J)
     dd = Jc.imag / h
     assert abs(np.sum(g * delta) - dd) <= 1e-11 * abs(dd), (np.sum(g * delta), dd)
+
+
+@pytest.mark.parametrize("split", [1, 2, 3, 4])
+def test_adjoint_refuses_other_split_forms(split):
+    """The C routines of the reverse mode are the transpose of the Blaisdell
+    residual only; they refuse any other split form themselves (status -1) and
+    leave their outputs untouched."""
+    p = P(8, split=split)
+    q = S.random_state(p.n, 81, smooth=True)
+    lam = S.random_field(p.shape, 82)
+    qbar = np.full(p.shape, 7.0)
+    with pytest.raises(ValueError):
+        O.residual_adjoint(p, q, lam, qbar)
+    assert np.all(qbar == 7.0)
+    with pytest.raises(ValueError):
+        O.dissipation_grad(p, 0.01, 1, O.init(p))
