@@ -155,6 +155,20 @@ size_t flow_integrals_workspace_bytes(const ns_params_t* params);
 int flow_integrals(const ns_params_t* params, const ns_prec_t* prec, const void* q,
                    void* workspace, double* out8, void* stream);
 
+/* flow_integrals() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, but the first pass's partial sums go to a
+ * static device array inside the library (4 MiB per device, held until the
+ * process ends) instead of a caller workspace, and the call allocates nothing.
+ * Grids whose flow_integrals_workspace_bytes() exceeds 4 MiB (more than 65536
+ * first-pass blocks; every cube up to 1024^3 fits) return NS_ERR_SHAPE.  All
+ * calls on one device share that array: calls that overlap in time on one
+ * device (different streams, or host threads) race and give wrong sums; calls
+ * ordered on one stream are safe.  The first call on a device looks up the
+ * array's device address (once per device). */
+int flow_integrals_noalloc(const ns_params_t* params, const ns_prec_t* prec, const void* q, double* out8,
+                           void* stream);
+
 /* Bytes of device workspace ns_residual_adjoint() needs: 18 fields of N values
  * of prec->q's type (velocity and R_bar-weighted velocity fields, the
  * symmetric viscous-work adjoint and the inner differences of the mixed

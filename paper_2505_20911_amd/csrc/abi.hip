@@ -318,6 +318,33 @@ int flow_integrals(const ns_params_t* params, const ns_prec_t* prec, const void*
   return hip_status(e, "flow_integrals");
 }
 
+int flow_integrals_noalloc(const ns_params_t* params, const ns_prec_t* prec, const void* q, double* out8,
+                           void* stream) {
+  tgv::Grid g;
+  Form f;
+  int rc = check_params(params, &g);
+  if (rc) return rc;
+  if ((rc = check_prec(prec, &f))) return rc;
+  if ((rc = check_ptr(q, "q")) || (rc = check_ptr(out8, "out8"))) return rc;
+  if ((rc = check_launch(tgv::integrals_work_items(g), "flow_integrals_noalloc"))) return rc;
+  const long long rows = tgv::integrals_blocks(g);
+  if (rows > tgv::kNoAllocRows)
+    return fail(NS_ERR_SHAPE, "flow_integrals_noalloc: the grid needs " + std::to_string(rows) +
+                                  " partial-sum rows, the static scratch holds " +
+                                  std::to_string(tgv::kNoAllocRows) +
+                                  " (flow_integrals_workspace_bytes() must be at most 4 MiB)");
+  hipStream_t st = as_stream(stream);
+  const tgv::Coef<double> c = make_coef<double>(params);
+  hipError_t e;
+  switch (prec->q) {
+    case NS_F64: e = tgv::launch_integrals_noalloc<double>(g, c, q, out8, st); break;
+    case NS_F32: e = tgv::launch_integrals_noalloc<float>(g, c, q, out8, st); break;
+    case NS_F16: e = tgv::launch_integrals_noalloc<tgv::f16>(g, c, q, out8, st); break;
+    default: return fail(NS_ERR_DTYPE, "unsupported q dtype for flow_integrals_noalloc");
+  }
+  return hip_status(e, "flow_integrals_noalloc");
+}
+
 }  // extern "C"
 
 namespace {

@@ -13,8 +13,17 @@
 // Deterministic two-pass reduction: pass 1 gives one row of 8 partial sums
 // per block (fixed point-to-thread mapping, wavefront shuffles then LDS
 // across waves); pass 2 sums the rows in a fixed order in a single block.
+#include <mutex>
+
 #include "tgv_device.h"
 #include "tgv_kernels.h"
+
+// Partial-sum rows of the allocation-free entry point (flow_integrals_noalloc):
+// 8 doubles per first-pass block, for grids of up to kNoAllocRows blocks
+// (4 MiB; every cube up to 1024^3).  Each device holds its own copy for the
+// life of the process.  In host code this name is not a device address: the
+// launcher takes the address from hipGetSymbolAddress, per device.
+static __device__ __align__(256) double scratch[tgv::kNoAllocRows * 8];
 
 namespace tgv {
 
@@ -228,6 +237,51 @@ hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q,
                      out8);
   return hipGetLastError();
 }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs `st` (the current device
+// for the null stream), looked up once per device with that device current.
+hipError_t noalloc_scratch(hipStream_t st, double** out) {
+  int cur = 0, dev = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  dev = cur;
+  if (st != nullptr && (e = hipStreamGetDevice(st, &dev)) != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+template <class Tq>
+hipError_t launch_integrals_noalloc(const Grid& g, const Coef<double>& c, const void* q, double* out8,
+                                    hipStream_t st) {
+  if (int_launch(g).blocks > kNoAllocRows) return hipErrorInvalidValue;  // the C-ABI refuses such grids first
+  double* work = nullptr;
+  const hipError_t e = noalloc_scratch(st, &work);
+  if (e != hipSuccess) return e;
+  return launch_integrals<Tq>(g, c, q, work, out8, st);
+}
+
+template hipError_t launch_integrals_noalloc<double>(const Grid&, const Coef<double>&, const void*, double*, hipStream_t);
+template hipError_t launch_integrals_noalloc<float>(const Grid&, const Coef<double>&, const void*, double*, hipStream_t);
+template hipError_t launch_integrals_noalloc<f16>(const Grid&, const Coef<double>&, const void*, double*, hipStream_t);
 
 template hipError_t launch_integrals<double>(const Grid&, const Coef<double>&, const void*, double*, double*, hipStream_t);
 template hipError_t launch_integrals<float>(const Grid&, const Coef<double>&, const void*, double*, double*, hipStream_t);

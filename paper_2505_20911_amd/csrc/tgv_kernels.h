@@ -37,6 +37,15 @@ template <class Tq>
 hipError_t launch_integrals(const Grid& g, const Coef<double>& c, const void* q, double* work,
                             double* out8, hipStream_t st);
 
+// The same two passes with the partial sums in the library's static device
+// scratch instead of a caller workspace; grids of more than kNoAllocRows
+// first-pass blocks do not fit it.
+constexpr long long kNoAllocRows = 1LL << 16;
+
+template <class Tq>
+hipError_t launch_integrals_noalloc(const Grid& g, const Coef<double>& c, const void* q, double* out8,
+                                    hipStream_t st);
+
 // Fields of N values the residual adjoint's workspace holds.
 constexpr int kResidualAdjointWorkFields = 18;
 

@@ -49,6 +49,8 @@ _EXPORTS = {
     "flow_integrals_workspace_bytes": ([ctypes.POINTER(NsParams)], ctypes.c_size_t),
     "flow_integrals": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "flow_integrals_noalloc": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ns_residual_adjoint_workspace_bytes": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec)], ctypes.c_size_t),
     "ns_residual_adjoint": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_void_p, ctypes.c_void_p,
                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -212,6 +214,14 @@ def flow_integrals(params: Params, prec: Prec, q: torch.Tensor, workspace: torch
     _check("flow_integrals", load().flow_integrals(ctypes.byref(params.c()), ctypes.byref(prec.c()),
                                                    _ptr(q, "q", prec.q, 5 * params.N), _ptr(workspace, "workspace"),
                                                    _ptr(out8, "out8", torch.float64, 8), _stream(stream)))
+
+
+def flow_integrals_noalloc(params: Params, prec: Prec, q: torch.Tensor, out8: torch.Tensor, stream=None) -> None:
+    """flow_integrals without a workspace (the library's static device scratch;
+    calls that overlap on one device race)."""
+    _check("flow_integrals_noalloc", load().flow_integrals_noalloc(
+        ctypes.byref(params.c()), ctypes.byref(prec.c()), _ptr(q, "q", prec.q, 5 * params.N),
+        _ptr(out8, "out8", torch.float64, 8), _stream(stream)))
 
 
 def ns_residual_adjoint_workspace_bytes(params: Params, prec: Prec) -> int:

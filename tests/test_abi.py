@@ -188,3 +188,19 @@ def test_grid_size_limits_are_validated_before_launch():
     rc = lib.flow_integrals_adjoint(ctypes.byref(thin.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
                                     ctypes.c_double(1.0), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None)
     assert rc == NS_ERR_SHAPE
+
+
+def test_noalloc_integrals_refuse_grids_beyond_the_static_scratch():
+    lib = tgv.load()
+    prec = tgv.PRESETS["DP"]
+    # 1088 x 1024 x 1024: 17 x 256 x 16 = 69632 first-pass blocks > 65536 rows
+    p = tgv.Params(n=(1088, 1024, 1024))
+    rc = lib.flow_integrals_noalloc(ctypes.byref(p.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
+                                    ctypes.c_void_p(0x2000), None)
+    assert rc == NS_ERR_SHAPE
+    assert "static scratch" in tgv.ns_last_error()
+    assert tgv.flow_integrals_workspace_bytes(p) > 4 << 20
+    # 1024^3 fits exactly (65536 rows, 4 MiB)
+    assert tgv.flow_integrals_workspace_bytes(tgv.Params(n=(1024, 1024, 1024))) == 4 << 20
+    rc = lib.flow_integrals_noalloc(ctypes.byref(p.c()), ctypes.byref(prec.c()), None, ctypes.c_void_p(0x2000), None)
+    assert rc == NS_ERR_ARG
