@@ -108,6 +108,39 @@ enum {
  * evaluated in FP64 and rounded to q_dtype.  Writes q [5][nz][ny][nx]. */
 int tgv_init(const ns_params_t* params, ns_dtype_t q_dtype, void* q, void* stream);
 
+/* The same Taylor-Green initial fields in primitive form: velocity u
+ * [3][nz][ny][nx], density rho and pressure p [nz][ny][nx], evaluated in FP64
+ * and rounded to dtype (NS_F64 or NS_F32).  u, rho, p: distinct 16-byte
+ * aligned device arrays. */
+int tgv_init_primitive(const ns_params_t* params, ns_dtype_t dtype, void* u, void* rho, void* p, void* stream);
+
+/* Conserved state of a velocity field at given density and pressure (Sec. 3.1
+ * state vector; the total energy rho E = p/(gamma-1) + rho |u|^2 / 2 of the
+ * equation of state above):
+ *   q = (rho, rho u, rho v, rho w, p/(gamma-1) + (rho/2)(u^2 + v^2 + w^2)),
+ * arithmetic and storage in dtype (NS_F64 or NS_F32).  This is how the
+ * differentiation form builds Q^0 from its control, the initial velocity
+ * (density and pressure held fixed).  u [3][N], rho [N], p [N] are read, q
+ * [5][N] written; q must not overlap the inputs. */
+int ns_state_from_velocity(const ns_params_t* params, ns_dtype_t dtype, const void* u, const void* rho,
+                           const void* p, void* q, void* stream);
+
+/* Reverse of ns_state_from_velocity at fixed rho and p:
+ *   u_bar_a = rho (q_bar_{m_a} + u_a q_bar_E),   a = 1..3,
+ * the gradient with respect to the velocity of a function of q whose gradient
+ * with respect to q is q_bar.  u_bar [3][N] is overwritten (not accumulated). */
+int ns_state_from_velocity_adjoint(const ns_params_t* params, ns_dtype_t dtype, const void* u, const void* rho,
+                                   const void* q_bar, void* u_bar, void* stream);
+
+/* Time-integrated dissipation by the trapezoid rule over a history of flow
+ * integrals (the objective of the differentiation form):
+ *   J = dt sum_{n=0}^{rows-1} w_n hist[n * stride + col],  w_0 = w_{rows-1} = 1/2, else 1
+ * (rows = 1: J = dt hist[col] / 2).  With stride 8 and col 2 over rows written
+ * by flow_integrals this is dt sum_n w_n eps_S(Q^n).  hist and J are device
+ * memory; one block sums in a fixed order, so J is deterministic. */
+int dissipation_trapezoid(const double* hist, int64_t rows, int32_t stride, int32_t col, double dt, double* J,
+                          void* stream);
+
 /* Residual R = dQ/dt (Sec. 3.1: R holds all terms of the equations except the
  * time derivative), 4th-order central differences for the convective and
  * diffusive parts (Sec. 2.3.1):

@@ -257,10 +257,29 @@ def dissipation_grad(P: Params, dt: float, nsteps: int, q0):
     return float(J[0]), g
 
 
+def init_primitive(P: Params):
+    """Taylor-Green initial fields in primitive form (Sec. 4.1 initial
+    condition, isothermal density rho = gamma M^2 p), FP64:
+    u (3, nz, ny, nx), rho and p (nz, ny, nx).  Plain NumPy on the grid
+    x_i = i L / n."""
+    nx, ny, nz = P.n
+    x = np.arange(nx) * (P.L[0] / nx)
+    y = np.arange(ny) * (P.L[1] / ny)
+    z = np.arange(nz) * (P.L[2] / nz)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u = np.empty((3, nz, ny, nx))
+    u[0] = np.sin(X) * np.cos(Y) * np.cos(Z)
+    u[1] = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    u[2] = 0.0
+    gm2 = P.gamma * P.mach ** 2
+    p = 1.0 / gm2 + (np.cos(2 * X) + np.cos(2 * Y)) * (2.0 + np.cos(2 * Z)) / 16.0
+    return u, gm2 * p, p
+
+
 def velocity_ic_state(P: Params, u0: np.ndarray, rho0: np.ndarray, p0: np.ndarray) -> np.ndarray:
     """Q^0 built from a velocity field u0 (3, nz, ny, nx) with the density and
     pressure fields held fixed: m = rho0 u0, rho E = p0/(gamma-1) + 1/2 rho0 |u0|^2."""
-    q = np.empty(P.shape, np.float64)
+    q = np.empty(P.shape, np.result_type(u0, rho0, p0, np.float64))
     q[0] = rho0
     q[1:4] = rho0[None] * u0
     q[4] = p0 / (P.gamma - 1.0) + 0.5 * rho0 * (u0 ** 2).sum(axis=0)

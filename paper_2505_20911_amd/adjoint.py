@@ -9,26 +9,37 @@ Y_0 = Q^{n-1}, Y_1, Y_2 re-taped from the restored state and zeta = 0,
 for i = 2, 1, 0:  zeta += B_i Q_bar ; R_bar = dt zeta ; zeta <- A_i zeta ;
 Q_bar += (dR/dQ)(Y_i)^T R_bar   (rk_stage_adjoint, ns_residual_adjoint),
 then Q_bar += dt w_{n-1} d(eps^S)/dQ(Y_0)   (flow_integrals_adjoint).
-Every arithmetic step runs in libtgv's kernels; this module sequences the
-calls and the snapshot copies.  The map from a velocity field to Q^0 is left
-to torch autograd (see ``state_from_velocity``), so gradients flow on to u0.
+The control is the initial velocity u0 with density and pressure held fixed:
+Q^0 = (rho0, rho0 u0, p0/(gamma-1) + rho0 |u0|^2 / 2) (ns_state_from_velocity),
+and dJ/du0 = rho0 (Q_bar_m + u0 Q_bar_E) (ns_state_from_velocity_adjoint).
+Every arithmetic step -- the state map, the time steps, the integrals, their
+adjoints and the trapezoid sum J -- runs in libtgv's kernels; this module
+sequences the calls and the snapshot copies.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import revolve, tgv
 from .tgv import Params, Prec
 
 
-def state_from_velocity(u0: torch.Tensor, rho0: torch.Tensor, p0: torch.Tensor, gamma: float) -> torch.Tensor:
-    """Q^0 from a velocity field (3, nz, ny, nx) with density and pressure held
-    fixed: (rho0, rho0 u0, p0/(gamma-1) + rho0 |u0|^2 / 2).  Plain torch ops,
-    differentiable, so torch autograd carries dJ/dQ^0 on to u0."""
-    m = rho0.unsqueeze(0) * u0
-    E = p0 / (gamma - 1.0) + 0.5 * rho0 * (u0 * u0).sum(0)
-    return torch.cat([rho0.unsqueeze(0), m, E.unsqueeze(0)], 0).contiguous()
+def state_from_velocity(u0: torch.Tensor, rho0: torch.Tensor, p0: torch.Tensor, params: Params) -> torch.Tensor:
+    """Q^0 (5, nz, ny, nx) from a velocity field (3, nz, ny, nx) at fixed
+    density and pressure (ns_state_from_velocity), in u0's dtype."""
+    q = torch.empty(params.shape, dtype=u0.dtype, device=u0.device)
+    tgv.ns_state_from_velocity(params, u0.detach().contiguous(), rho0.contiguous(), p0.contiguous(), q)
+    return q
+
+
+def taylor_green_primitive(params: Params, dtype=torch.float64, device="cuda"):
+    """(u0, rho0, p0) of the Taylor-Green initial state (tgv_init_primitive)."""
+    nx, ny, nz = params.n
+    u = torch.empty((3, nz, ny, nx), dtype=dtype, device=device)
+    rho = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+    p = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+    tgv.tgv_init_primitive(params, u, rho, p)
+    return u, rho, p
 
 
 class CheckpointedDissipation:
@@ -56,6 +67,7 @@ class CheckpointedDissipation:
         self.ewrk = torch.empty(tgv.flow_integrals_adjoint_workspace_bytes(params, prec) // 8 + 1,
                                 dtype=torch.float64, device=self.device)
         self.eps = torch.zeros((self.l + 1, 8), dtype=torch.float64, device=self.device)
+        self.J = torch.zeros(1, dtype=torch.float64, device=self.device)
         self.actions = revolve.schedule(self.l, self.slots) if self.l > 0 else []
         self.advances = 0
 
@@ -88,7 +100,11 @@ class CheckpointedDissipation:
 
     def forward(self, q0: torch.Tensor) -> float:
         """Runs the schedule's first descent (storing its snapshots) and one
-        extra step to Q^l; returns J."""
+        extra step to Q^l; returns J (synchronising on it)."""
+        return float(self.forward_device(q0)[0])
+
+    def forward_device(self, q0: torch.Tensor) -> torch.Tensor:
+        """As forward, returning J as a one-element device tensor (no host sync)."""
         self.cur.copy_(q0)
         self._integrals(self.cur, 0)
         n = 0
@@ -110,10 +126,10 @@ class CheckpointedDissipation:
             self.qlast.copy_(self.cur)
             self.qlast = self._step(self.qlast)
             self._integrals(self.qlast, self.l)
-        eps = self.eps[:, 2].cpu().numpy()
-        w = np.ones(self.l + 1)
-        w[0] = w[-1] = 0.5
-        return float(self.dt * np.dot(w, eps)) if self.l > 0 else 0.0
+        # J = dt sum_n w_n eps^S(Q^n), trapezoid weights (with l = 0 the one
+        # row has weight 1/2, as the reverse sweep's seed)
+        tgv.dissipation_trapezoid(self.eps, self.l + 1, self.dt, self.J)
+        return self.J
 
     # -- reverse pieces
     def _reverse_step(self, n: int, scale: float) -> None:
@@ -134,7 +150,8 @@ class CheckpointedDissipation:
         self.qbar.zero_()
         self.zeta.zero_()
         if self.l == 0:
-            tgv.flow_integrals_adjoint(self.params, self.prec, q0, scale * self.dt, self.qbar, self.ewrk)
+            tgv.flow_integrals_adjoint(self.params, self.prec, q0, scale * self.dt * self.weight(0), self.qbar,
+                                       self.ewrk)
             return self.qbar.clone()
         tgv.flow_integrals_adjoint(self.params, self.prec, self.qlast, scale * self.dt * self.weight(self.l),
                                    self.qbar, self.ewrk)
@@ -152,24 +169,32 @@ class CheckpointedDissipation:
 
 
 class TGVDissipation(torch.autograd.Function):
-    """J(Q^0) = dt sum_n w_n eps^S(Q^n) over `nsteps` RK3 steps; backward
-    returns dJ/dQ^0 through the discrete adjoint with revolve checkpointing."""
+    """J(u0) = dt sum_n w_n eps^S(Q^n) over `nsteps` RK3 steps from
+    Q^0 = state_from_velocity(u0, rho0, p0); backward returns dJ/du0 through
+    the discrete adjoint with revolve checkpointing and the adjoint of the
+    state map (rho0 and p0 are held fixed and get no gradient)."""
 
     @staticmethod
-    def forward(ctx, q0: torch.Tensor, runner: CheckpointedDissipation):
-        q0c = q0.detach().contiguous()
-        J = runner.forward(q0c)
+    def forward(ctx, u0: torch.Tensor, rho0: torch.Tensor, p0: torch.Tensor, runner: CheckpointedDissipation):
+        u0c = u0.detach().contiguous()
+        rho0c = rho0.detach().contiguous()
+        q0 = state_from_velocity(u0c, rho0c, p0.detach(), runner.params)
+        J = runner.forward_device(q0)
         ctx.runner = runner
-        ctx.save_for_backward(q0c)
-        return torch.tensor(J, dtype=torch.float64, device=q0.device)
+        ctx.save_for_backward(q0, u0c, rho0c)
+        return J[0].clone()
 
     @staticmethod
     def backward(ctx, gJ):
-        (q0,) = ctx.saved_tensors
-        g = ctx.runner.backward(q0, float(gJ))
-        return g, None
+        q0, u0, rho0 = ctx.saved_tensors
+        qbar = ctx.runner.backward(q0, float(gJ))
+        ubar = torch.empty_like(u0)
+        tgv.ns_state_from_velocity_adjoint(ctx.runner.params, u0, rho0, qbar, ubar)
+        return ubar, None, None, None
 
 
-def dissipation(q0: torch.Tensor, params: Params, prec: Prec, dt: float, nsteps: int, slots: int = 20):
-    runner = CheckpointedDissipation(params, prec, dt, nsteps, slots, device=q0.device)
-    return TGVDissipation.apply(q0, runner)
+def dissipation(u0: torch.Tensor, rho0: torch.Tensor, p0: torch.Tensor, params: Params, prec: Prec, dt: float,
+                nsteps: int, slots: int = 20) -> torch.Tensor:
+    """J(u0) as a differentiable scalar (TGVDissipation)."""
+    runner = CheckpointedDissipation(params, prec, dt, nsteps, slots, device=u0.device)
+    return TGVDissipation.apply(u0, rho0, p0, runner)

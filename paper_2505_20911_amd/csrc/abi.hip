@@ -179,6 +179,68 @@ int tgv_init(const ns_params_t* params, ns_dtype_t q_dtype, void* q, void* strea
   return hip_status(e, "tgv_init");
 }
 
+int tgv_init_primitive(const ns_params_t* params, ns_dtype_t dtype, void* u, void* rho, void* p, void* stream) {
+  tgv::Grid g;
+  int rc = check_params(params, &g);
+  if (rc) return rc;
+  if ((rc = check_ptr(u, "u")) || (rc = check_ptr(rho, "rho")) || (rc = check_ptr(p, "p"))) return rc;
+  if (u == rho || u == p || rho == p) return fail(NS_ERR_ARG, "u, rho and p must be distinct arrays");
+  hipError_t e;
+  switch (dtype) {
+    case NS_F64: e = tgv::launch_init_primitive<double>(g, params->L, params->gamma, params->mach, u, rho, p, as_stream(stream)); break;
+    case NS_F32: e = tgv::launch_init_primitive<float>(g, params->L, params->gamma, params->mach, u, rho, p, as_stream(stream)); break;
+    default: return fail(NS_ERR_DTYPE, "dtype must be NS_F64 or NS_F32");
+  }
+  return hip_status(e, "tgv_init_primitive");
+}
+
+int ns_state_from_velocity(const ns_params_t* params, ns_dtype_t dtype, const void* u, const void* rho,
+                           const void* p, void* q, void* stream) {
+  tgv::Grid g;
+  int rc = check_params(params, &g);
+  if (rc) return rc;
+  if ((rc = check_ptr(u, "u")) || (rc = check_ptr(rho, "rho")) || (rc = check_ptr(p, "p")) ||
+      (rc = check_ptr(q, "q")))
+    return rc;
+  if (q == u || q == rho || q == p) return fail(NS_ERR_ARG, "q must not overlap the inputs");
+  hipError_t e;
+  switch (dtype) {
+    case NS_F64: e = tgv::launch_state_from_velocity<double>(g, params->gamma, u, rho, p, q, as_stream(stream)); break;
+    case NS_F32: e = tgv::launch_state_from_velocity<float>(g, params->gamma, u, rho, p, q, as_stream(stream)); break;
+    default: return fail(NS_ERR_DTYPE, "dtype must be NS_F64 or NS_F32");
+  }
+  return hip_status(e, "ns_state_from_velocity");
+}
+
+int ns_state_from_velocity_adjoint(const ns_params_t* params, ns_dtype_t dtype, const void* u, const void* rho,
+                                   const void* q_bar, void* u_bar, void* stream) {
+  tgv::Grid g;
+  int rc = check_params(params, &g);
+  if (rc) return rc;
+  if ((rc = check_ptr(u, "u")) || (rc = check_ptr(rho, "rho")) || (rc = check_ptr(q_bar, "q_bar")) ||
+      (rc = check_ptr(u_bar, "u_bar")))
+    return rc;
+  if (u_bar == u || u_bar == rho || u_bar == q_bar) return fail(NS_ERR_ARG, "u_bar must not overlap the inputs");
+  hipError_t e;
+  switch (dtype) {
+    case NS_F64: e = tgv::launch_state_from_velocity_adjoint<double>(g, u, rho, q_bar, u_bar, as_stream(stream)); break;
+    case NS_F32: e = tgv::launch_state_from_velocity_adjoint<float>(g, u, rho, q_bar, u_bar, as_stream(stream)); break;
+    default: return fail(NS_ERR_DTYPE, "dtype must be NS_F64 or NS_F32");
+  }
+  return hip_status(e, "ns_state_from_velocity_adjoint");
+}
+
+int dissipation_trapezoid(const double* hist, int64_t rows, int32_t stride, int32_t col, double dt, double* J,
+                          void* stream) {
+  if (!hist || !J) return fail(NS_ERR_ARG, "hist and J must not be NULL");
+  if (reinterpret_cast<uintptr_t>(hist) % 8 != 0 || reinterpret_cast<uintptr_t>(J) % 8 != 0)
+    return fail(NS_ERR_ALIGN, "hist and J must be 8-byte aligned");
+  if (rows < 1) return fail(NS_ERR_ARG, "rows must be >= 1");
+  if (stride < 1 || col < 0 || col >= stride) return fail(NS_ERR_ARG, "need 0 <= col < stride");
+  if (!std::isfinite(dt)) return fail(NS_ERR_ARG, "dt must be finite");
+  return hip_status(tgv::launch_trapezoid(hist, rows, stride, col, dt, J, as_stream(stream)), "dissipation_trapezoid");
+}
+
 int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q, void* r, void* stream) {
   tgv::Grid g;
   Form f;

@@ -18,6 +18,21 @@ template <class Tq>
 hipError_t launch_init(const Grid& g, const double L[3], double gamma, double mach, void* q,
                        hipStream_t st);
 
+template <class T>
+hipError_t launch_init_primitive(const Grid& g, const double L[3], double gamma, double mach, void* u, void* rho,
+                                 void* p, hipStream_t st);
+
+template <class T>
+hipError_t launch_state_from_velocity(const Grid& g, double gamma, const void* u, const void* rho, const void* p,
+                                      void* q, hipStream_t st);
+
+template <class T>
+hipError_t launch_state_from_velocity_adjoint(const Grid& g, const void* u, const void* rho, const void* qbar,
+                                              void* ubar, hipStream_t st);
+
+hipError_t launch_trapezoid(const double* h, long long rows, int stride, int col, double dt, double* out,
+                            hipStream_t st);
+
 template <class Tq, class Tr, class Tc>
 hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, int split, const void* q, void* r, hipStream_t st);
 

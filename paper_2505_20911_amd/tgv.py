@@ -40,6 +40,14 @@ class NsPrec(ctypes.Structure):
 _lib = None
 _EXPORTS = {
     "tgv_init": ([ctypes.POINTER(NsParams), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tgv_init_primitive": ([ctypes.POINTER(NsParams), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ns_state_from_velocity": ([ctypes.POINTER(NsParams), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ns_state_from_velocity_adjoint": ([ctypes.POINTER(NsParams), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "dissipation_trapezoid": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                               ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ns_residual": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.c_void_p], ctypes.c_int),
     "rk_stage": ([ctypes.POINTER(NsParams), ctypes.POINTER(NsPrec), ctypes.c_int, ctypes.c_double,
@@ -178,6 +186,46 @@ def tgv_init(params: Params, q: torch.Tensor, stream=None) -> None:
         raise TypeError(f"unsupported dtype {q.dtype}")
     _check("tgv_init", load().tgv_init(ctypes.byref(params.c()), code, _ptr(q, "q", numel=5 * params.N),
                                        _stream(stream)))
+
+
+def _code(dtype: torch.dtype) -> int:
+    code = _CODE_OF.get(dtype)
+    if code is None:
+        raise TypeError(f"unsupported dtype {dtype}")
+    return code
+
+
+def tgv_init_primitive(params: Params, u: torch.Tensor, rho: torch.Tensor, p: torch.Tensor, stream=None) -> None:
+    N = params.N
+    _check("tgv_init_primitive", load().tgv_init_primitive(
+        ctypes.byref(params.c()), _code(u.dtype), _ptr(u, "u", u.dtype, 3 * N), _ptr(rho, "rho", u.dtype, N),
+        _ptr(p, "p", u.dtype, N), _stream(stream)))
+
+
+def ns_state_from_velocity(params: Params, u: torch.Tensor, rho: torch.Tensor, p: torch.Tensor, q: torch.Tensor,
+                           stream=None) -> None:
+    N = params.N
+    _check("ns_state_from_velocity", load().ns_state_from_velocity(
+        ctypes.byref(params.c()), _code(u.dtype), _ptr(u, "u", u.dtype, 3 * N), _ptr(rho, "rho", u.dtype, N),
+        _ptr(p, "p", u.dtype, N), _ptr(q, "q", u.dtype, 5 * N), _stream(stream)))
+
+
+def ns_state_from_velocity_adjoint(params: Params, u: torch.Tensor, rho: torch.Tensor, q_bar: torch.Tensor,
+                                   u_bar: torch.Tensor, stream=None) -> None:
+    N = params.N
+    _check("ns_state_from_velocity_adjoint", load().ns_state_from_velocity_adjoint(
+        ctypes.byref(params.c()), _code(u.dtype), _ptr(u, "u", u.dtype, 3 * N), _ptr(rho, "rho", u.dtype, N),
+        _ptr(q_bar, "q_bar", u.dtype, 5 * N), _ptr(u_bar, "u_bar", u.dtype, 3 * N), _stream(stream)))
+
+
+def dissipation_trapezoid(hist: torch.Tensor, rows: int, dt: float, J: torch.Tensor, stride: int = 8, col: int = 2,
+                          stream=None) -> None:
+    """J[0] = dt sum_n w_n hist[n, col] over the first `rows` rows (trapezoid weights)."""
+    if hist.dim() != 2 or hist.shape[1] != stride or hist.shape[0] < rows:
+        raise ValueError(f"hist must be ({rows}+, {stride})")
+    _check("dissipation_trapezoid", load().dissipation_trapezoid(
+        _ptr(hist, "hist", torch.float64), int(rows), int(stride), int(col), float(dt), _ptr(J, "J", torch.float64, 1),
+        _stream(stream)))
 
 
 def ns_residual(params: Params, prec: Prec, q: torch.Tensor, r: torch.Tensor, stream=None) -> None:

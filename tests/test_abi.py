@@ -204,3 +204,18 @@ def test_noalloc_integrals_refuse_grids_beyond_the_static_scratch():
     assert tgv.flow_integrals_workspace_bytes(tgv.Params(n=(1024, 1024, 1024))) == 4 << 20
     rc = lib.flow_integrals_noalloc(ctypes.byref(p.c()), ctypes.byref(prec.c()), None, ctypes.c_void_p(0x2000), None)
     assert rc == NS_ERR_ARG
+
+
+def test_state_map_and_trapezoid_validate_on_the_host():
+    lib = tgv.load()
+    p = tgv.Params(n=(8, 8, 8))
+    a, b, c, d = (ctypes.c_void_p(x) for x in (0x1000, 0x2000, 0x3000, 0x4000))
+    assert lib.ns_state_from_velocity(ctypes.byref(p.c()), tgv.NS_F16, a, b, c, d, None) == NS_ERR_DTYPE
+    assert lib.ns_state_from_velocity(ctypes.byref(p.c()), tgv.NS_F64, a, b, c, a, None) == NS_ERR_ARG
+    assert lib.ns_state_from_velocity(ctypes.byref(p.c()), tgv.NS_F64, None, b, c, d, None) == NS_ERR_ARG
+    assert lib.ns_state_from_velocity_adjoint(ctypes.byref(p.c()), tgv.NS_F64, a, b, c,
+                                              ctypes.c_void_p(0x4008), None) == NS_ERR_ALIGN
+    assert lib.tgv_init_primitive(ctypes.byref(tgv.Params(n=(4, 8, 8)).c()), tgv.NS_F64, a, b, c, None) == NS_ERR_SHAPE
+    assert lib.dissipation_trapezoid(a, 0, 8, 2, 1e-3, b, None) == NS_ERR_ARG
+    assert lib.dissipation_trapezoid(a, 5, 8, 8, 1e-3, b, None) == NS_ERR_ARG
+    assert lib.dissipation_trapezoid(None, 5, 8, 2, 1e-3, b, None) == NS_ERR_ARG

@@ -11,8 +11,9 @@ import torch
 import oracle as O
 import tgv_synth as S
 from paper_2505_20911_amd import tgv
-from paper_2505_20911_amd.adjoint import CheckpointedDissipation, TGVDissipation, dissipation, state_from_velocity
-from tgv_testutil import oracle_params, widened
+from paper_2505_20911_amd.adjoint import (CheckpointedDissipation, dissipation, state_from_velocity,
+                                          taylor_green_primitive)
+from tgv_testutil import UNIT_ROUNDOFF, adjoint_term_scale, oracle_params, rounded, widened
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -49,20 +50,68 @@ def test_residual_adjoint_dp_matches_oracle(n, kind, viscous):
     assert np.all(err <= 1e-11 * scale), err / scale
 
 
-def test_residual_adjoint_sp_within_rounding():
-    n = (12, 16, 10)
+# Grids on which the gather kernel runs its benchmark launch: full 16-plane
+# column chunks (the launch shortens them only when a grid has fewer than 2048
+# blocks of 64 x 4 columns), a block count divisible by 8 (XCD-contiguous block
+# order on), ragged x (69 of 2 x 64 columns), y (126 = 31.5 x 4) and z
+# (497 = 31 x 16 + 1: a one-plane last chunk), and 31 chunk seams along z.
+FULL_LAUNCH_GRIDS = [(69, 126, 497)]
+
+
+def _col_march(n):
+    """Chunk height and block count of the gather launch on grid n (the rule
+    the kernel's launcher applies)."""
+    tx, ty, kz = -(-n[0] // 64), -(-n[1] // 4), 16
+    while kz > 1 and tx * ty * -(-n[2] // kz) < 2048:
+        kz //= 2
+    return kz, tx * ty * -(-n[2] // kz)
+
+
+@pytest.mark.parametrize("n", FULL_LAUNCH_GRIDS)
+@pytest.mark.parametrize("viscous", [1, 0])
+def test_residual_adjoint_dp_matches_oracle_in_the_full_launch(n, viscous):
+    kz, blocks = _col_march(n)
+    assert kz == 16 and blocks % 8 == 0 and n[2] % kz != 0
+    say("adjoint DP full launch", n, viscous, "kz", kz, "blocks", blocks)
+    p = tgv.Params(n=n, viscous=viscous)
+    q64 = S.random_state(n, 15, smooth=True)
+    rbar = S.random_field(p.shape, 16)
+    qb0 = S.random_field(p.shape, 17)
+    ref = O.residual_adjoint(oracle_params(p), q64, rbar, qb0.copy())
+    prec = tgv.PRESETS["DP"]
+    qb = torch.from_numpy(qb0).to(DEV)
+    tgv.ns_residual_adjoint(p, prec, torch.from_numpy(q64).to(DEV), torch.from_numpy(rbar).to(DEV), qb,
+                            work_for(p, prec, tgv.ns_residual_adjoint_workspace_bytes))
+    got = qb.cpu().numpy()
+    scale = np.abs(ref - qb0).reshape(5, -1).max(1)
+    err = np.abs(got - ref).reshape(5, -1).max(1)
+    say("  err / max|adjoint|", err / scale)
+    assert np.all(err <= 1e-12 * scale), err / scale
+
+
+@pytest.mark.parametrize("n", [(12, 16, 10)] + FULL_LAUNCH_GRIDS)
+@pytest.mark.parametrize("kind", ["tgv", "smooth"])
+def test_residual_adjoint_sp_within_rounding(n, kind):
+    """FP32 storage and arithmetic: the inputs rounded to FP32 are the common
+    input (the oracle sees them widened exactly); the GPU result may differ by
+    FP32 rounding on the adjoint's term scale (the same factor 64 of the unit
+    roundoff as the forward residual's bound) plus one rounding of Q_bar."""
+    say("adjoint SP", n, kind)
     p = tgv.Params(n=n)
-    q32 = torch.from_numpy(S.random_state(n, 5, smooth=True)).float()
-    r32 = torch.from_numpy(S.random_field(p.shape, 6)).float()
+    q64 = O.init(oracle_params(p)) if kind == "tgv" else S.random_state(n, 5, smooth=True)
+    q32 = rounded(q64, torch.float32)
+    r32 = rounded(S.random_field(p.shape, 6), torch.float32)
     ref = O.residual_adjoint(oracle_params(p), widened(q32), widened(r32))
     prec = tgv.PRESETS["SP"]
     qb = torch.zeros(p.shape, dtype=torch.float32, device=DEV)
     tgv.ns_residual_adjoint(p, prec, q32.to(DEV), r32.to(DEV), qb,
                             work_for(p, prec, tgv.ns_residual_adjoint_workspace_bytes))
-    scale = np.abs(ref).reshape(5, -1).max(1)
-    err = np.abs(widened(qb) - ref).reshape(5, -1).max(1)
-    say("  SP err / max|adjoint|", err / scale)
-    assert np.all(err <= 2e-3 * scale)
+    u = UNIT_ROUNDOFF[torch.float32]
+    scale = adjoint_term_scale(p, widened(q32), widened(r32))
+    err = np.abs(widened(qb) - ref)
+    say("  SP err / (u * adjoint term scale)", (err / (u * scale)).reshape(5, -1).max(1),
+        "max|adjoint| / term scale", np.abs(ref).max() / scale)
+    assert np.all(err <= 64 * u * scale + 2 * u * np.abs(ref))
 
 
 @pytest.mark.parametrize("n", [(12, 16, 10), (5, 6, 7)])
@@ -124,30 +173,84 @@ def test_checkpointed_gradient_bitwise_equals_store_all():
 
 
 def test_autograd_velocity_gradient_matches_finite_differences():
-    """dJ/du0 through torch autograd (state_from_velocity) and the revolve
-    adjoint, against central differences with eps = 1e-6 along seeded
-    Gaussian directions (unnormalised)."""
+    """dJ/du0 through the autograd function (the state map and its adjoint in
+    the library) and the revolve adjoint, against central differences with
+    eps = 1e-6 along seeded Gaussian directions (unnormalised), and against
+    the oracle's store-all gradient carried to u0 by its chain rule."""
     n, dt, nsteps = (16, 16, 16), 0.02, 20
     p = tgv.Params(n=n)
-    q0 = torch.from_numpy(O.init(oracle_params(p))).to(DEV)
-    rho0 = q0[0].clone()
-    u0 = (q0[1:4] / rho0).clone().requires_grad_(True)
-    E = q0[4] - 0.5 * rho0 * (q0[1:4] / rho0).pow(2).sum(0)
-    p0 = E * (p.gamma - 1.0)
-    J = dissipation(state_from_velocity(u0, rho0, p0, p.gamma), p, tgv.PRESETS["DP"], dt, nsteps, slots=4)
+    u0, rho0, p0 = taylor_green_primitive(p)
+    uu = u0.clone().requires_grad_(True)
+    J = dissipation(uu, rho0, p0, p, tgv.PRESETS["DP"], dt, nsteps, slots=4)
     J.backward()
-    g = u0.grad.detach()
+    g = uu.grad.detach()
+    po = oracle_params(p)
+    uo, ro, pro = O.init_primitive(po)
+    J_ref, gq_ref = O.dissipation_grad(po, dt, nsteps, O.velocity_ic_state(po, uo, ro, pro))
+    g_ref = O.velocity_grad_from_state_grad(po, gq_ref, uo, ro)
+    assert abs(float(J.detach()) - J_ref) <= 1e-13 * abs(J_ref)
+    rel = float(np.linalg.norm(g.cpu().numpy() - g_ref) / np.linalg.norm(g_ref))
+    say("  velocity gradient vs oracle, rel L2", rel)
+    assert rel <= 1e-11
     runner = CheckpointedDissipation(p, tgv.PRESETS["DP"], dt, nsteps, slots=4)
     eps = 1e-6
     for s in range(2):
         d = torch.from_numpy(S.directions(n, s)).to(DEV)
-        with torch.no_grad():
-            Jp = runner.forward(state_from_velocity(u0 + eps * d, rho0, p0, p.gamma))
-            Jm = runner.forward(state_from_velocity(u0 - eps * d, rho0, p0, p.gamma))
+        Jp = runner.forward(state_from_velocity(u0 + eps * d, rho0, p0, p))
+        Jm = runner.forward(state_from_velocity(u0 - eps * d, rho0, p0, p))
         fd = (Jp - Jm) / (2 * eps)
         ad = float((g * d).sum())
         say("  FD", fd, "AD", ad)
         assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (69, 20, 37)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_velocity_state_map_and_adjoint_match_oracle(n, dtype):
+    """tgv_init_primitive, ns_state_from_velocity and its adjoint against the
+    oracle's initial fields, velocity_ic_state and its chain rule (on the
+    rounded inputs, widened exactly, for FP32)."""
+    say("state map", n, dtype)
+    p = tgv.Params(n=n)
+    po = oracle_params(p)
+    u, rho, pr = taylor_green_primitive(p, dtype)
+    uo, ro, pro = O.init_primitive(po)
+    u_ref = 1e-300 + np.abs(uo).max()
+    if dtype == torch.float64:
+        assert np.all(np.abs(widened(u) - uo) <= 4e-16 * u_ref)
+        assert np.all(np.abs(widened(rho) - ro) <= 4e-16 * ro)
+        assert np.all(np.abs(widened(pr) - pro) <= 4e-16 * pro)
+    else:
+        ur = UNIT_ROUNDOFF[dtype]
+        assert np.all(np.abs(widened(u) - uo) <= ur * np.abs(uo) + 4e-16 * u_ref)
+        assert np.all(np.abs(widened(rho) - ro) <= ur * ro)
+        assert np.all(np.abs(widened(pr) - pro) <= ur * pro)
+    # a perturbed velocity (not a symmetric field) through the state map
+    d = rounded(0.1 * S.directions(n, 3), dtype).to(DEV)
+    uu = u + d
+    q = state_from_velocity(uu, rho, pr, p)
+    q_ref = O.velocity_ic_state(po, widened(uu), widened(rho), widened(pr))
+    uc = UNIT_ROUNDOFF[dtype]
+    assert np.all(np.abs(widened(q) - q_ref) <= 4 * uc * np.abs(q_ref).reshape(5, -1).max(1)[:, None, None, None])
+    qbar = rounded(S.random_field(p.shape, 9), dtype).to(DEV)
+    ub = torch.empty_like(uu)
+    tgv.ns_state_from_velocity_adjoint(p, uu, rho, qbar, ub)
+    ub_ref = O.velocity_grad_from_state_grad(po, widened(qbar), widened(uu), widened(rho))
+    scale = np.abs(widened(rho)).max() * (np.abs(widened(qbar)).max() * (1 + np.abs(widened(uu)).max()))
+    assert np.all(np.abs(widened(ub) - ub_ref) <= 4 * uc * scale)
+
+
+@pytest.mark.parametrize("rows", [1, 2, 3, 401, 1000])
+def test_dissipation_trapezoid(rows):
+    """J = dt sum_n w_n h[n, 2] with w_0 = w_{rows-1} = 1/2 (one row: 1/2),
+    against an exactly rounded sum of the same terms."""
+    import math
+    h = S.random_field((rows, 8), rows) ** 2
+    J = torch.empty(1, dtype=torch.float64, device=DEV)
+    tgv.dissipation_trapezoid(torch.from_numpy(h).to(DEV), rows, 9.25e-4, J)
+    w = [0.5 if k in (0, rows - 1) else 1.0 for k in range(rows)]
+    ref = 9.25e-4 * math.fsum(wk * hk for wk, hk in zip(w, h[:, 2]))
+    assert abs(float(J) - ref) <= 2 * rows * 2.0 ** -53 * abs(ref)
 
 
 @pytest.mark.parametrize("viscous", [1, 0])

@@ -93,6 +93,41 @@ def test_ic_pointwise_evaluator(n):
         np.testing.assert_allclose(O.init_at(p, lin), rows[:, 3:], rtol=1e-14, atol=1e-14)
 
 
+def test_ic_primitive_fields():
+    """init_primitive (u, rho, p) at the hand-evaluated points of the golden
+    fixture (velocity = momentum / rho there, p from rho = gamma M^2 p), and
+    the state it gives through velocity_ic_state equals init."""
+    p = P(8)
+    u, rho, pr = O.init_primitive(p)
+    rows = np.loadtxt(os.path.join(GOLDEN, "tgv_ic_special_points.txt"))
+    for r in rows:
+        i, j, k = int(r[0]), int(r[1]), int(r[2])
+        np.testing.assert_allclose(rho[k, j, i], r[3], rtol=1e-15)
+        np.testing.assert_allclose(u[:, k, j, i], r[4:7] / r[3], rtol=1e-15, atol=1e-16)
+        np.testing.assert_allclose(pr[k, j, i], r[3] / (1.4 * 0.01), rtol=1e-15)
+    for n in (8, (12, 20, 16)):
+        p = P(n)
+        u, rho, pr = O.init_primitive(p)
+        np.testing.assert_allclose(O.velocity_ic_state(p, u, rho, pr), O.init(p), rtol=4e-16, atol=4e-16)
+
+
+def test_velocity_state_chain_rule_by_complex_step():
+    """velocity_grad_from_state_grad is the gradient of <q_bar, Q(u)> with
+    respect to u for the map velocity_ic_state (density and pressure fixed):
+    the complex-step derivative along a direction d equals <u_bar, d>."""
+    p = P((6, 7, 5))
+    u = S.random_field((3,) + p.shape[1:], 1) * 0.3
+    rho = 1.0 + 0.1 * S.random_field(p.shape[1:], 2)
+    pr = 70.0 + S.random_field(p.shape[1:], 3)
+    qbar = S.random_field(p.shape, 4)
+    ub = O.velocity_grad_from_state_grad(p, qbar, u, rho)
+    for seed in (5, 6):
+        d = S.random_field(u.shape, seed)
+        h = 1e-30
+        jd = (qbar * O.velocity_ic_state(p, u + 1j * h * d, rho, pr)).sum().imag / h
+        assert abs(jd - (ub * d).sum()) <= 1e-13 * np.abs(ub * d).sum()
+
+
 @pytest.mark.parametrize("n", [8, 16, 32])
 def test_ic_reflection_symmetries(n):
     """u odd in x, v odd in y, w = 0, scalars even under each reflection x_d -> -x_d."""
