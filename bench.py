@@ -22,7 +22,8 @@ if ROOT not in sys.path:
 
 METRIC = "Mpt·stage/s + % HBM peak, TGV 512^3: FP64 vs half-single/single-double"
 HBM_PEAK_GBS = 8000.0
-ALL_FORMS = ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"]
+ALL_FORMS = ["DP", "SPDP", "SPDP_C64", "SPDP_WK", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HPSP_WK", "HPSP_RESWK", "HP",
+             "HP_C16"]
 
 
 def parse():

@@ -28,7 +28,7 @@ int ok() {
 }
 
 // The supported precision forms (q, qt, r, compute).
-enum Form { DP, SPDP, SPDP_C64, SP_DPC, SP, HPSP, HPSP_BF16, HP, BAD };
+enum Form { DP, SPDP, SPDP_C64, SP_DPC, SP, HPSP, HPSP_BF16, HP, SPDP_WK, HPSP_WK, HPSP_RESWK, HP_C16, BAD };
 
 Form form_of(const ns_prec_t& p) {
   auto is = [&](ns_dtype_t a, ns_dtype_t b, ns_dtype_t c, ns_dtype_t d) {
@@ -42,6 +42,10 @@ Form form_of(const ns_prec_t& p) {
   if (is(NS_F32, NS_F32, NS_F16, NS_F32)) return HPSP;
   if (is(NS_F32, NS_F32, NS_BF16, NS_F32)) return HPSP_BF16;
   if (is(NS_F16, NS_F16, NS_F16, NS_F32)) return HP;
+  if (is(NS_F64, NS_F64, NS_F64, NS_F32)) return SPDP_WK;
+  if (is(NS_F32, NS_F32, NS_F32, NS_F16)) return HPSP_WK;
+  if (is(NS_F32, NS_F32, NS_F16, NS_F16)) return HPSP_RESWK;
+  if (is(NS_F16, NS_F16, NS_F16, NS_F16)) return HP_C16;
   return BAD;
 }
 
@@ -263,6 +267,10 @@ int ns_residual(const ns_params_t* params, const ns_prec_t* prec, const void* q,
     case HPSP: e = tgv::launch_residual<float, f16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
     case HPSP_BF16: e = tgv::launch_residual<float, bf16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
     case HP: e = tgv::launch_residual<f16, f16, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case SPDP_WK: e = tgv::launch_residual<double, double, float>(g, make_coef<float>(params), params->split, q, r, st); break;
+    case HPSP_WK: e = tgv::launch_residual<float, float, f16>(g, make_coef<f16>(params), params->split, q, r, st); break;
+    case HPSP_RESWK: e = tgv::launch_residual<float, f16, f16>(g, make_coef<f16>(params), params->split, q, r, st); break;
+    case HP_C16: e = tgv::launch_residual<f16, f16, f16>(g, make_coef<f16>(params), params->split, q, r, st); break;
     default: break;
   }
   return hip_status(e, "ns_residual");
@@ -284,14 +292,18 @@ int rk_stage(const ns_params_t* params, const ns_prec_t* prec, int stage, double
   using tgv::bf16;
   using tgv::f16;
   switch (f) {
-    case DP: e = tgv::launch_rk_stage<double, double, double, double>(g, stage, dt, q, qt, r, st); break;
+    case DP:
+    case SPDP_WK: e = tgv::launch_rk_stage<double, double, double, double>(g, stage, dt, q, qt, r, st); break;
     case SPDP:
     case SPDP_C64: e = tgv::launch_rk_stage<double, double, float, double>(g, stage, dt, q, qt, r, st); break;
     case SP_DPC: e = tgv::launch_rk_stage<float, float, float, double>(g, stage, dt, q, qt, r, st); break;
-    case SP: e = tgv::launch_rk_stage<float, float, float, float>(g, stage, dt, q, qt, r, st); break;
-    case HPSP: e = tgv::launch_rk_stage<float, float, f16, float>(g, stage, dt, q, qt, r, st); break;
+    case SP:
+    case HPSP_WK: e = tgv::launch_rk_stage<float, float, float, float>(g, stage, dt, q, qt, r, st); break;
+    case HPSP:
+    case HPSP_RESWK: e = tgv::launch_rk_stage<float, float, f16, float>(g, stage, dt, q, qt, r, st); break;
     case HPSP_BF16: e = tgv::launch_rk_stage<float, float, bf16, float>(g, stage, dt, q, qt, r, st); break;
-    case HP: e = tgv::launch_rk_stage<f16, f16, f16, float>(g, stage, dt, q, qt, r, st); break;
+    case HP:
+    case HP_C16: e = tgv::launch_rk_stage<f16, f16, f16, float>(g, stage, dt, q, qt, r, st); break;
     default: break;
   }
   return hip_status(e, "rk_stage");
@@ -345,6 +357,22 @@ int ns_residual_rk_stage(const ns_params_t* params, const ns_prec_t* prec, int s
     case HP:
       e = tgv::launch_residual_rk<f16, f16, f16, float, float>(g, make_coef<float>(params), params->split, stage, dt, q_in, q_out, qt,
                                                                st);
+      break;
+    case SPDP_WK:
+      e = tgv::launch_residual_rk<double, double, double, float, double>(g, make_coef<float>(params), params->split, stage, dt,
+                                                                         q_in, q_out, qt, st);
+      break;
+    case HPSP_WK:
+      e = tgv::launch_residual_rk<float, float, float, f16, float>(g, make_coef<f16>(params), params->split, stage, dt, q_in,
+                                                                   q_out, qt, st);
+      break;
+    case HPSP_RESWK:
+      e = tgv::launch_residual_rk<float, float, f16, f16, float>(g, make_coef<f16>(params), params->split, stage, dt, q_in,
+                                                                 q_out, qt, st);
+      break;
+    case HP_C16:
+      e = tgv::launch_residual_rk<f16, f16, f16, f16, float>(g, make_coef<f16>(params), params->split, stage, dt, q_in, q_out,
+                                                             qt, st);
       break;
     default: break;
   }

@@ -125,6 +125,39 @@ __device__ __forceinline__ void primitives(const Tc q[5], Tc* out, const Coef<Tc
   out[F_T] = c.gm2 * p * ir;
 }
 
+// x-neighbour s (0..3 = -2, -1, +1, +2 points) of LDS slot i in a row.  With
+// packed FP16 pairs a slot holds two x-points, so the +-2 neighbours are the
+// adjacent slots and the +-1 neighbours straddle two slots.
+template <class Tc>
+__device__ __forceinline__ Tc xnb(const Tc* row, int i, int s) {
+  if constexpr (kLanes<Tc> == 1) {
+    return row[i + ((s < 2) ? (s - 2) : (s - 1))];
+  } else {
+    if (s == 0) return row[i - 1];
+    if (s == 3) return row[i + 1];
+    return s == 1 ? __builtin_shufflevector(row[i - 1], row[i], 1, 2)
+                  : __builtin_shufflevector(row[i], row[i + 1], 1, 2);
+  }
+}
+
+// The four x-neighbours of slot i from per-slot values at i - 1, i, i + 1
+// (packed pairs), or at i - 2 .. i + 2 through `at` (one point per slot).
+template <class Tc, class F>
+__device__ __forceinline__ void xnb4(F at, int i, Tc (&out)[4]) {
+  if constexpr (kLanes<Tc> == 1) {
+    out[0] = at(i - 2);
+    out[1] = at(i - 1);
+    out[2] = at(i + 1);
+    out[3] = at(i + 2);
+  } else {
+    const Tc a = at(i - 1), b = at(i), d = at(i + 1);
+    out[0] = a;
+    out[1] = __builtin_shufflevector(a, b, 1, 2);
+    out[2] = __builtin_shufflevector(b, d, 1, 2);
+    out[3] = d;
+  }
+}
+
 // Neighbour accessors: field f at offset index s (0..3 = -2, -1, +1, +2)
 // along one direction, from the LDS plane (x, y) or the z-window.
 template <class Tc, int STRIDE, int PLANE = NPL>
@@ -132,6 +165,7 @@ struct LdsNb {
   const Tc* lds;
   int own;
   __device__ __forceinline__ Tc operator()(int f, int s) const {
+    if constexpr (STRIDE == 1) return xnb(lds + f * PLANE, own, s);
     const int o = (s < 2) ? (s - 2) : (s - 1);
     return lds[f * PLANE + own + o * STRIDE];
   }
@@ -602,21 +636,29 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
 // plane.  A run never crosses the periodic wrap in x and is V-element aligned
 // when nx is even (tile origins and the halo width are even); odd nx takes
 // V = 1.
-template <int WTX, int WTY, int V = 1>
+// Geometry in LDS slots: a slot is one x-point, or P = 2 consecutive x-points
+// for the packed FP16 arithmetic (the tile is then 2 WTX points wide and the
+// 2-point halo is one slot).  Loads of the plane go in runs of V slots.
+template <int WTX, int WTY, int V = 1, int P = 1>
 struct Ws {
-  static constexpr int TX = WTX, HX = WTX + 4, TY = WTY, NCOL = WTX * WTY, NT = 2 * NCOL, HY = WTY + 4,
+  static constexpr int HALO = 2 / P;
+  static constexpr int TX = WTX, HX = WTX + 2 * HALO, TY = WTY, NCOL = WTX * WTY, NT = 2 * NCOL, HY = WTY + 4,
                        NPL = HX * HY;
   static_assert(HX % V == 0, "a load run must not cross a halo row");
+  static_assert(P == 1 || V == 1, "packed pairs load one slot per run");
   static constexpr int VPR = HX / V, NVS = NPL / V;  // runs per halo row and per plane
   static constexpr int LOADS = (NVS + NCOL - 1) / NCOL;
 };
 #define TGV_WS_DIMS                                                                          \
-  constexpr int WS_TX = Ws<WTX, WTY>::TX, WS_HX = Ws<WTX, WTY>::HX, WS_TY = Ws<WTX, WTY>::TY;     \
-  constexpr int WS_NCOL = Ws<WTX, WTY>::NCOL, WS_NPL = Ws<WTX, WTY>::NPL;                 \
-  (void)WS_TY;
+  constexpr int WS_P = kLanes<Tc>, WS_HALO = Ws<WTX, WTY, 1, WS_P>::HALO;                    \
+  constexpr int WS_TX = Ws<WTX, WTY, 1, WS_P>::TX, WS_HX = Ws<WTX, WTY, 1, WS_P>::HX;       \
+  constexpr int WS_TY = Ws<WTX, WTY, 1, WS_P>::TY;                                          \
+  constexpr int WS_NCOL = Ws<WTX, WTY, 1, WS_P>::NCOL, WS_NPL = Ws<WTX, WTY, 1, WS_P>::NPL;  \
+  (void)WS_TY;                                                                               \
+  (void)WS_HALO;
 #define TGV_WS_RUNS                                                                          \
-  constexpr int WS_VPR = Ws<WTX, WTY, V>::VPR, WS_NVS = Ws<WTX, WTY, V>::NVS;              \
-  constexpr int WS_LOADS = Ws<WTX, WTY, V>::LOADS;
+  constexpr int WS_VPR = Ws<WTX, WTY, V, WS_P>::VPR, WS_NVS = Ws<WTX, WTY, V, WS_P>::NVS;    \
+  constexpr int WS_LOADS = Ws<WTX, WTY, V, WS_P>::LOADS;
 
 
 // The warp-specialised kernel keeps the reduced window (conserved variables
@@ -651,7 +693,7 @@ template <class Tc, int SPLIT, int WTX, int WTY>
 __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ring_r, Tc* ring_a, int col) {
   TGV_WS_DIMS
   const int tx = col % WS_TX, ty = col / WS_TX;
-  const int own = (ty + 2) * WS_HX + (tx + 2);
+  const int own = (ty + 2) * WS_HX + (tx + WS_HALO);
   Tc c0[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) c0[k] = lds[k * WS_NPL + own];
@@ -673,20 +715,19 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
     }
   }
   if (c.viscous) {
+    // X_x += D_x D_y v: x-differences of v on the rows y +- 1, 2; X_y +=
+    // D_y D_x u: y-differences of u at the x-neighbour columns
     const int offs[4] = {-2, -1, 1, 2};
     Tc iv[4], iu[4];
+    const Tc* vp = lds + (F_U + 1) * WS_NPL;
+    const Tc* up = lds + F_U * WS_NPL;
 #pragma unroll
     for (int sy = 0; sy < 4; ++sy) {
       const int row = own + offs[sy] * WS_HX;
-      iv[sy] = S1(lds[(F_U + 1) * WS_NPL + row - 2], lds[(F_U + 1) * WS_NPL + row - 1], lds[(F_U + 1) * WS_NPL + row + 1],
-                  lds[(F_U + 1) * WS_NPL + row + 2]);
+      iv[sy] = S1(xnb(vp, row, 0), xnb(vp, row, 1), xnb(vp, row, 2), xnb(vp, row, 3));
     }
-#pragma unroll
-    for (int sx = 0; sx < 4; ++sx) {
-      const int cl = own + offs[sx];
-      iu[sx] = S1(lds[F_U * WS_NPL + cl - 2 * WS_HX], lds[F_U * WS_NPL + cl - WS_HX], lds[F_U * WS_NPL + cl + WS_HX],
-                  lds[F_U * WS_NPL + cl + 2 * WS_HX]);
-    }
+    xnb4<Tc>([&](int cl) { return S1(up[cl - 2 * WS_HX], up[cl - WS_HX], up[cl + WS_HX], up[cl + 2 * WS_HX]); },
+             own, iu);
     const Tc cxy = c.c1[0] * c.c1[1] * c.ire * Tc(1.0 / 3.0);
     const Tc mx = cxy * S1(iv[0], iv[1], iv[2], iv[3]);
     const Tc my = cxy * S1(iu[0], iu[1], iu[2], iu[3]);
@@ -700,25 +741,111 @@ __device__ __forceinline__ void ip_step(const Coef<Tc>& c, const Tc* lds, Tc* ri
   for (int a = 0; a < 3; ++a) ring_a[a * WS_NCOL + col] = A3[a];
 }
 
+// Register type of the prefetched plane: the arithmetic type, or for packed
+// FP16 pairs the stored pair itself, converted only when the plane is written
+// to LDS a step later (a conversion right after the load would make the
+// prefetch wait for its data).
+template <class Tq, class Tc>
+struct NxtOf {
+  using type = Tc;
+};
+template <class Tq>
+struct NxtOf<Tq, h2> {
+  using type = Run<Tq, 2>;
+};
+template <>
+struct NxtOf<f16, h2> {  // the stored pair is already the lane value
+  using type = h2;
+};
+template <class Tc, class Tq, int N>
+__device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_load(const Tq (&e)[N], int i) {
+  if constexpr (kLanes<Tc> == 1)
+    return load_as<Tc>(e[i]);
+  else if constexpr (std::is_same<Tq, f16>::value)
+    return h2{e[2 * i], e[2 * i + 1]};
+  else
+    return Run<Tq, 2>{{e[2 * i], e[2 * i + 1]}};
+}
+template <class Tc, class N>
+__device__ __forceinline__ Tc nxt_value(const N& v) {
+  if constexpr (kLanes<Tc> == 1 || std::is_same<N, h2>::value)
+    return v;
+  else
+    return lane_load<Tc>(v.e);
+}
+template <class Tc, class Tq>
+__device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_pad() {
+  if constexpr (kLanes<Tc> == 1)
+    return Tc(1);
+  else if constexpr (std::is_same<Tq, f16>::value)
+    return h2{f16(1), f16(1)};
+  else
+    return Run<Tq, 2>{{Tq(1), Tq(1)}};
+}
+
+// Two consecutive values in one nontemporal vector access (packed lanes).
+template <class T>
+__device__ __forceinline__ void stream_store2(T* p, T a, T b) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(V2{a, b}, reinterpret_cast<V2*>(p));
+}
+template <class T>
+__device__ __forceinline__ void stream_load2(const T* p, T& a, T& b) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+  a = v.x;
+  b = v.y;
+}
+
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int V, int PH>
 __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, ZCtx<Tc>& zc,
                                        QRing6<Tq>& qr, const Tc* cur, Tc* next, const Tc* ring_r,
                                        const Tc* ring_a_prev, bool have_prev,
-                                       Tc (&nxt)[Ws<WTX, WTY, V>::LOADS][V][5],
-                                       const long long (&off)[Ws<WTX, WTY, V>::LOADS], int p, int z0, int z1,
-                                       int p_last, bool col_valid, long long col_off, int zt) {
+                                       typename NxtOf<Tq, Tc>::type (&nxt)[Ws<WTX, WTY, V, kLanes<Tc>>::LOADS][V][5],
+                                       const long long (&off)[Ws<WTX, WTY, V, kLanes<Tc>>::LOADS], int p, int z0,
+                                       int z1, int p_last, bool col_valid, long long col_off, int zt) {
   TGV_WS_DIMS
   TGV_WS_RUNS
-  constexpr bool kQinFromWindow = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
+  constexpr int P = WS_P;
+  // the window holds Q converted exactly when each point's arithmetic type is
+  // at least as wide as its storage type
+  constexpr bool kQinFromWindow =
+      sizeof(typename LaneT<Tc>::E) >= sizeof(Tq) && (std::is_same<Ta, Tc>::value || P == 2);
+  // Q_in of the emitted point otherwise: a register ring of the own column's
+  // stored values (one point per lane), or, for packed pairs, re-read at
+  // emission (three planes after the block loaded it)
+  constexpr bool kQinRing = !kQinFromWindow && P == 1;
   const Grid& g = K.g;
   const Coef<Tc>& c = K.c;
   const int k = p - 3;
   const bool emit = k >= z0 && k < z1;
-  Tqt qt_k[5] = {Tqt(), Tqt(), Tqt(), Tqt(), Tqt()};
+  Tqt qt_k[5][P];
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int e = 0; e < P; ++e) qt_k[f][e] = Tqt();
   if (FUSED && emit && col_valid && !rk.first) {
     const long long id = (long long)k * g.plane + col_off;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qt_k[f] = stream_load(&rk.qt[f * g.N + id]);
+    for (int f = 0; f < 5; ++f) {
+      if constexpr (P == 1)
+        qt_k[f][0] = stream_load(&rk.qt[f * g.N + id]);
+      else
+        stream_load2(&rk.qt[f * g.N + id], qt_k[f][0], qt_k[f][1]);
+    }
+  }
+  // packed pairs: Q_in of the emitted points, requested with the register
+  Tq qin_k[5][P];
+  if constexpr (FUSED && !kQinFromWindow && !kQinRing) {
+    if (emit && col_valid) {
+      const long long id = (long long)k * g.plane + col_off;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const Run<Tq, P> v = *reinterpret_cast<const Run<Tq, P>*>(K.q + f * g.N + id);
+#pragma unroll
+        for (int e = 0; e < P; ++e) qin_k[f][e] = v.e[e];
+      }
+    }
   }
   // 1. primitives of plane p + 1 into the other buffer; loads of plane p + 2
   if (p + 1 <= p_last) {
@@ -729,8 +856,10 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
         const int s0 = (sv / WS_VPR) * WS_HX + (sv % WS_VPR) * V;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          Tc f[NF];
-          primitives(nxt[l][e], f, c);
+          Tc qv[5], f[NF];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) qv[m] = nxt_value<Tc>(nxt[l][e][m]);
+          primitives(qv, f, c);
 #pragma unroll
           for (int m = 0; m < NF; ++m) next[m * WS_NPL + s0 + e] = f[m];
         }
@@ -747,9 +876,9 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
         if (sv < WS_NVS) {
 #pragma unroll
           for (int f = 0; f < 5; ++f) {
-            const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
+            const Run<Tq, V * P> v = *reinterpret_cast<const Run<Tq, V * P>*>(K.q + f * g.N + zo + off[l]);
 #pragma unroll
-            for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+            for (int e = 0; e < V; ++e) nxt[l][e][f] = nxt_load<Tc>(v.e, e);
           }
         }
       }
@@ -758,17 +887,19 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
   // 2. own column of plane p into window slot PH
   if (p <= p_last) {
     const int tx = zt % WS_TX, ty = zt / WS_TX;
-    const int own = (ty + 2) * WS_HX + (tx + 2);
+    const int own = (ty + 2) * WS_HX + (tx + WS_HALO);
     Tc c0[NF];
 #pragma unroll
     for (int m = 0; m < NF; ++m) c0[m] = cur[m * WS_NPL + own];
 #pragma unroll
     for (int m = 0; m < 5; ++m) zc.W[PH][m] = c0[m];
     zc.W[PH][W_IR] = recip(c0[F_RHO]);
-    if (FUSED && !kQinFromWindow && p >= z0 && p < z1 && col_valid) {
-      const long long id = (long long)p * g.plane + col_off;
+    if constexpr (FUSED && kQinRing) {
+      if (p >= z0 && p < z1 && col_valid) {
+        const long long id = (long long)p * g.plane + col_off;
 #pragma unroll
-      for (int f = 0; f < 5; ++f) qr.v[PH][f] = K.q[f * g.N + id];
+        for (int f = 0; f < 5; ++f) qr.v[PH][f] = K.q[f * g.N + id];
+      }
     }
   }
   // 3. gradient combinations of plane p - 1
@@ -807,19 +938,37 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
       const long long id = (long long)k * g.plane + col_off;
       if (!FUSED) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) stream_store(&K.r[f * g.N + id], store_as<Tr>(Rz[f]));
+        for (int f = 0; f < 5; ++f) {
+          if constexpr (P == 1)
+            stream_store(&K.r[f * g.N + id], store_as<Tr>(Rz[f]));
+          else
+            stream_store2(&K.r[f * g.N + id], store_as<Tr>(lane_get(Rz[f], 0)), store_as<Tr>(lane_get(Rz[f], 1)));
+        }
       } else {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          const Ta rr = load_as<Ta>(store_as<Tr>(Rz[f]));
-          const Tqt ts = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f]), rr));
-          stream_store(&rk.qt[f * g.N + id], ts);
-          Ta qin;
-          if constexpr (kQinFromWindow)
-            qin = ck[f];
-          else
-            qin = load_as<Ta>(qr.v[K0][f]);
-          stream_store(&rk.q_out[f * g.N + id], store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts))));
+          Tqt ts[P];
+          Tq qo[P];
+#pragma unroll
+          for (int e = 0; e < P; ++e) {
+            const Ta rr = load_as<Ta>(store_as<Tr>(lane_get(Rz[f], e)));
+            ts[e] = store_as<Tqt>(rk_register<Ta>(rk.first, rk.A, rk.dt, load_as<Ta>(qt_k[f][e]), rr));
+            Ta qin;
+            if constexpr (kQinFromWindow)
+              qin = load_as<Ta>(lane_get(ck[f], e));
+            else if constexpr (kQinRing)
+              qin = load_as<Ta>(qr.v[K0][f]);
+            else
+              qin = load_as<Ta>(qin_k[f][e]);
+            qo[e] = store_as<Tq>(rk_state<Ta>(rk.B, qin, load_as<Ta>(ts[e])));
+          }
+          if constexpr (P == 1) {
+            stream_store(&rk.qt[f * g.N + id], ts[0]);
+            stream_store(&rk.q_out[f * g.N + id], qo[0]);
+          } else {
+            stream_store2(&rk.qt[f * g.N + id], ts[0], ts[1]);
+            stream_store2(&rk.q_out[f * g.N + id], qo[0], qo[1]);
+          }
         }
       }
     }
@@ -841,7 +990,7 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
   const int tx_t = b % tiles_x;
   const int ty_t = (b / tiles_x) % tiles_y;
   const int cz = b / (tiles_y * tiles_x);
-  const int x0 = tx_t * WS_TX, y0 = ty_t * WS_TY;
+  const int x0 = tx_t * WS_TX * WS_P, y0 = ty_t * WS_TY;  // in grid points
   const int z0 = cz * kz;
   const int z1 = min(z0 + kz, g.nz);
   const bool zrole = threadIdx.x >= WS_NCOL;
@@ -851,18 +1000,18 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
 #pragma unroll
   for (int l = 0; l < WS_LOADS; ++l) {
     const int sv = col + l * WS_NCOL;
-    const int lx = (sv % WS_VPR) * V, ly = sv / WS_VPR;
+    const int lx = (sv % WS_VPR) * V * WS_P, ly = sv / WS_VPR;
     int x = (x0 - 2 + lx) % g.nx;
     x += (x < 0) ? g.nx : 0;
     int y = (y0 - 2 + ly) % g.ny;
     y += (y < 0) ? g.ny : 0;
     off[l] = (long long)y * g.nx + x;
   }
-  const int cxg = x0 + col % WS_TX, cyg = y0 + col / WS_TX;
-  const bool col_valid = cxg < g.nx && cyg < g.ny;
+  const int cxg = x0 + (col % WS_TX) * WS_P, cyg = y0 + col / WS_TX;
+  const bool col_valid = cxg < g.nx && cyg < g.ny;  // nx is even for pairs: both points in the grid
   const long long col_off = (long long)cyg * g.nx + cxg;
   const int p_first = z0 - 2, p_last = z1 + 1;  // planes entering the window
-  Tc nxt[WS_LOADS][V][5];
+  typename NxtOf<Tq, Tc>::type nxt[WS_LOADS][V][5];
   if (zrole) {
     // plane p_first into buffer 0, plane p_first + 1 into registers
     for (int h = 0; h < 2; ++h) {
@@ -875,10 +1024,10 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
         const int sv = col + l * WS_NCOL;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          Run<Tq, V> v;
-          if (sv < WS_NVS) v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
+          Run<Tq, V * WS_P> v;
+          if (sv < WS_NVS) v = *reinterpret_cast<const Run<Tq, V * WS_P>*>(K.q + f * g.N + zo + off[l]);
 #pragma unroll
-          for (int e = 0; e < V; ++e) nxt[l][e][f] = sv < WS_NVS ? load_as<Tc>(v.e[e]) : Tc(1);
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = sv < WS_NVS ? nxt_load<Tc>(v.e, e) : nxt_pad<Tc, Tq>();
         }
       }
       if (h == 0) {
@@ -889,8 +1038,10 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_
             const int s0 = (sv / WS_VPR) * WS_HX + (sv % WS_VPR) * V;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              Tc f[NF];
-              primitives(nxt[l][e], f, K.c);
+              Tc qv[5], f[NF];
+#pragma unroll
+              for (int m = 0; m < 5; ++m) qv[m] = nxt_value<Tc>(nxt[l][e][m]);
+              primitives(qv, f, K.c);
 #pragma unroll
               for (int m = 0; m < NF; ++m) lds[0][m * WS_NPL + s0 + e] = f[m];
             }
@@ -951,13 +1102,40 @@ TileLaunch tile_launch(const Grid& g, int tx, int ty) {
 
 }  // namespace
 
+// Packed FP16 tile: 32 x 8 lanes of two x-points (64 x 8 grid points), two
+// roles of 256 threads at two waves per SIMD (with 32 x 16 lanes and 128
+// registers the kernel spills 18-22 of them).
+constexpr int kH2Tx = 32, kH2Ty = 8;
+
 long long residual_work_items(const Grid& g) {
-  // the three launch geometries: warp-specialised 32 x 8 (512 threads) and
-  // 64 x 8 (1024 threads), single-role 64 x 8 (512 threads)
+  // the launch geometries: warp-specialised 32 x 8 (512 threads), 64 x 8
+  // (1024 threads) and packed 64 x 16 points (1024 threads), single-role
+  // 64 x 8 (512 threads)
   const long long a = tile_launch(g, 32, 8).blocks * Ws<32, 8>::NT;
   const long long b = tile_launch(g, 64, 8).blocks * Ws<64, 8>::NT;
   const long long c = tile_launch(g, TX, TY).blocks * NT;
-  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+  const long long d = tile_launch(g, 2 * kH2Tx, kH2Ty).blocks * Ws<kH2Tx, kH2Ty>::NT;
+  const long long m = a > b ? (a > c ? a : c) : (b > c ? b : c);
+  return m > d ? m : d;
+}
+
+// FP16 arithmetic coefficients as packed pairs.
+Coef<h2> splat(const Coef<f16>& c) {
+  Coef<h2> o;
+  auto sp = [](f16 v) { return h2{v, v}; };
+  for (int d = 0; d < 3; ++d) {
+    o.c1[d] = sp(c.c1[d]);
+    o.c2[d] = sp(c.c2[d]);
+    o.vis2[d] = sp(c.vis2[d]);
+    o.vis2l[d] = sp(c.vis2l[d]);
+    o.kap2[d] = sp(c.kap2[d]);
+  }
+  o.gm1 = sp(c.gm1);
+  o.gm2 = sp(c.gm2);
+  o.ire = sp(c.ire);
+  o.kap = sp(c.kap);
+  o.viscous = c.viscous;
+  return o;
 }
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT>
@@ -970,6 +1148,19 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   // single-role kernel for two forms where it is faster: the fused stage
   // with FP64 Q and FP32 arithmetic (its Q_in ring does not fit the z role's
   // registers) and FP32 Q with FP64 arithmetic.
+  if constexpr (std::is_same<Tc, f16>::value) {
+    // FP16 arithmetic: packed pairs of x-points in the warp-specialised
+    // kernel when nx is even (pairs never cross the periodic wrap and are
+    // aligned); one point per lane otherwise.
+    if (g.nx % 2 == 0) {
+      const TileLaunch L = tile_launch(g, 2 * kH2Tx, kH2Ty);
+      const int remap = L.blocks % 8 == 0 ? 1 : 0;
+      Kernel<Tq, Tr, h2> K{g, splat(c), static_cast<const Tq*>(q), static_cast<Tr*>(r)};
+      hipLaunchKernelGGL((residual_ws<Tq, Tr, h2, Tqt, Ta, FUSED, SPLIT, kH2Tx, kH2Ty, 1>), dim3((unsigned)L.blocks),
+                         dim3(Ws<kH2Tx, kH2Ty>::NT), 0, st, K, rk, L.tiles_x, L.tiles_y, L.kz, remap);
+      return hipGetLastError();
+    }
+  }
   constexpr bool kQinExact = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
   constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8) && !(sizeof(Tc) == 8 && sizeof(Tq) < 8);
   constexpr int kWtx = sizeof(Tc) == 8 ? 32 : 64, kWty = 8;
@@ -1029,8 +1220,10 @@ hipError_t launch_split(int split, const Grid& g, const Coef<Tc>& c, const void*
 
 template <class Tq, class Tr, class Tc>
 hipError_t launch_residual(const Grid& g, const Coef<Tc>& c, int split, const void* q, void* r, hipStream_t st) {
-  const RkArgs<Tq, Tq, Tc> none{nullptr, nullptr, Tc(0), Tc(0), Tc(0), 1};
-  return launch_split<Tq, Tr, Tc, Tq, Tc, false>(split, g, c, q, r, none, st);
+  // (the stage arguments are unused; their arithmetic type is FP32 for FP16 arithmetic)
+  using Ta = typename std::conditional<std::is_same<Tc, f16>::value, float, Tc>::type;
+  const RkArgs<Tq, Tq, Ta> none{nullptr, nullptr, Ta(0), Ta(0), Ta(0), 1};
+  return launch_split<Tq, Tr, Tc, Tq, Ta, false>(split, g, c, q, r, none, st);
 }
 
 template <class Tq, class Tqt, class Tr, class Tc, class Ta>
@@ -1053,6 +1246,10 @@ TGV_INST_RES(float, float, float)
 TGV_INST_RES(float, f16, float)
 TGV_INST_RES(float, bf16, float)
 TGV_INST_RES(f16, f16, float)
+TGV_INST_RES(double, double, float)
+TGV_INST_RES(float, float, f16)
+TGV_INST_RES(float, f16, f16)
+TGV_INST_RES(f16, f16, f16)
 
 #define TGV_INST_RRK(Tq, Tqt, Tr, Tc, Ta)                                                                     \
   template hipError_t launch_residual_rk<Tq, Tqt, Tr, Tc, Ta>(const Grid&, const Coef<Tc>&, int, int, double,\
@@ -1065,5 +1262,9 @@ TGV_INST_RRK(float, float, float, float, float)
 TGV_INST_RRK(float, float, f16, float, float)
 TGV_INST_RRK(float, float, bf16, float, float)
 TGV_INST_RRK(f16, f16, f16, float, float)
+TGV_INST_RRK(double, double, double, float, double)
+TGV_INST_RRK(float, float, float, f16, float)
+TGV_INST_RRK(float, float, f16, f16, float)
+TGV_INST_RRK(f16, f16, f16, f16, float)
 
 }  // namespace tgv

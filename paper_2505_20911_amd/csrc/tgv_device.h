@@ -14,6 +14,9 @@ struct bf16 {
 };
 
 using f16 = _Float16;
+// Two FP16 values in one 32-bit register: arithmetic on it is element-wise
+// and compiles to the packed FP16 VALU instructions (two results per lane).
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t f32_bits(float x) { return __builtin_bit_cast(uint32_t, x); }
 __device__ __forceinline__ float bits_f32(uint32_t u) { return __builtin_bit_cast(float, u); }
@@ -51,6 +54,7 @@ struct Conv<double> {
   __device__ __forceinline__ static float load_f32(double v) { return (float)v; }
   __device__ __forceinline__ static double from(double x) { return x; }
   __device__ __forceinline__ static double from(float x) { return (double)x; }
+  __device__ __forceinline__ static double from(_Float16 x) { return (double)(float)x; }
 };
 
 template <>
@@ -59,14 +63,16 @@ struct Conv<float> {
   __device__ __forceinline__ static float load_f32(float v) { return v; }
   __device__ __forceinline__ static float from(double x) { return (float)x; }
   __device__ __forceinline__ static float from(float x) { return x; }
+  __device__ __forceinline__ static float from(_Float16 x) { return (float)x; }
 };
 
 // An FP32 value is first rounded in FP32 and then to FP16 (the arithmetic
 // type, then the storage type).  The empty asm pins the FP32 value so the
 // compiler cannot merge a producing fma with the conversion into a mixed
-// fma that rounds only once.
+// fma that rounds only once.  It is not volatile: a volatile asm would also
+// be a scheduling boundary for everything around it.
 __device__ __forceinline__ f16 f32_to_f16(float x) {
-  asm volatile("" : "+v"(x));
+  asm("" : "+v"(x));
   return (f16)x;
 }
 
@@ -76,6 +82,7 @@ struct Conv<f16> {
   __device__ __forceinline__ static float load_f32(f16 v) { return (float)v; }
   __device__ __forceinline__ static f16 from(double x) { return f32_to_f16(f64_to_f32_odd(x)); }
   __device__ __forceinline__ static f16 from(float x) { return f32_to_f16(x); }
+  __device__ __forceinline__ static f16 from(f16 x) { return x; }
 };
 
 template <>
@@ -107,6 +114,41 @@ template <>
 __device__ __forceinline__ float load_as<float, f16>(f16 v) { return (float)v; }
 template <>
 __device__ __forceinline__ float load_as<float, bf16>(bf16 v) { return Conv<bf16>::load_f32(v); }
+// (a value read from memory has no producing fma to merge with: plain RNE)
+template <>
+__device__ __forceinline__ f16 load_as<f16, float>(float v) { return (f16)v; }
+template <>
+__device__ __forceinline__ f16 load_as<f16, f16>(f16 v) { return v; }
+
+// Points per lane of an arithmetic type: 2 for the packed FP16 pair, else 1;
+// lane_get reads point e of a lane value.
+template <class Tc>
+struct LaneT {
+  static constexpr int P = 1;
+  using E = Tc;
+};
+template <>
+struct LaneT<h2> {
+  static constexpr int P = 2;
+  using E = f16;
+};
+template <class Tc>
+constexpr int kLanes = LaneT<Tc>::P;
+template <class Tc>
+__device__ __forceinline__ typename LaneT<Tc>::E lane_get(Tc v, int e) {
+  if constexpr (kLanes<Tc> == 1)
+    return v;
+  else
+    return e == 0 ? v.x : v.y;
+}
+// A lane value from P consecutive stored points.
+template <class Tc, class T>
+__device__ __forceinline__ Tc lane_load(const T* pts) {
+  if constexpr (kLanes<Tc> == 1)
+    return load_as<Tc>(pts[0]);
+  else
+    return h2{load_as<f16>(pts[0]), load_as<f16>(pts[1])};
+}
 
 // Store an arithmetic value into storage type T (RNE, correctly rounded).
 // Store that streams past the caches (the nontemporal hint on a vector
@@ -163,6 +205,9 @@ __device__ __forceinline__ float recip(float x) {
   float r = __builtin_amdgcn_rcpf(x);
   return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
 }
+// FP16 arithmetic: the FP32 reciprocal rounded once to FP16.
+__device__ __forceinline__ f16 recip(f16 x) { return f32_to_f16(recip((float)x)); }
+__device__ __forceinline__ h2 recip(h2 x) { return h2{recip(x.x), recip(x.y)}; }
 
 // One-dimensional launches: a dispatch holds fewer than 2^32 work-items, so
 // element-wise kernels loop grid-stride over their index range and their block

@@ -150,6 +150,13 @@ PRESETS = {
     "HPSP": Prec(f32, f32, f16, f32),
     "HPSP_BF16": Prec(f32, f32, bf16, f32),
     "HP": Prec(f16, f16, f16, f32),
+    # per-class variants (Sec. 4.2): "-wk" reduces only the work quantities,
+    # here the arithmetic; "-res" only R; "-res+wk" both.  SPDP is SPDP-res+wk,
+    # SPDP_C64 SPDP-res, HPSP HPSP-res.
+    "SPDP_WK": Prec(f64, f64, f64, f32),
+    "HPSP_WK": Prec(f32, f32, f32, f16),
+    "HPSP_RESWK": Prec(f32, f32, f16, f16),
+    "HP_C16": Prec(f16, f16, f16, f16),
 }
 
 

@@ -79,7 +79,8 @@ def test_residual_dp_matches_oracle(n, kind, viscous):
 
 
 # ---------------------------------------------------------------- residual, reduced forms
-@pytest.mark.parametrize("form", ["SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"])
+@pytest.mark.parametrize("form", ["SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP", "SPDP_WK", "HPSP_WK",
+                                  "HPSP_RESWK", "HP_C16"])
 @pytest.mark.parametrize("kind", ["tgv", "smooth"])
 @pytest.mark.parametrize("n", [(24, 32, 16), (69, 20, 17)])  # odd nx: single-element plane loads
 def test_residual_reduced_forms_within_rounding_bound(form, kind, n):
@@ -131,7 +132,8 @@ def test_residual_is_deterministic():
 
 
 # ---------------------------------------------------------------- RK stage
-@pytest.mark.parametrize("form", ["DP", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"])
+@pytest.mark.parametrize("form", ["DP", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP", "SPDP_WK", "HPSP_WK",
+                                  "HPSP_RESWK", "HP_C16"])
 @pytest.mark.parametrize("stage", [0, 1, 2])
 def test_rk_stage_matches_oracle(form, stage):
     say("rk", form, stage)
@@ -173,8 +175,9 @@ def test_rk_stage_matches_oracle(form, stage):
 
 
 # ---------------------------------------------------------------- fused residual + RK stage
-@pytest.mark.parametrize("form", ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"])
-@pytest.mark.parametrize("n", [(24, 32, 40), (5, 6, 7), (64, 8, 70), (69, 20, 37)])
+@pytest.mark.parametrize("form", ["DP", "SPDP", "SPDP_C64", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP", "SPDP_WK",
+                                  "HPSP_WK", "HPSP_RESWK", "HP_C16"])
+@pytest.mark.parametrize("n", [(24, 32, 40), (5, 6, 7), (64, 8, 70), (69, 20, 37), (130, 20, 9)])
 def test_fused_stage_equals_residual_then_stage(form, n):
     """ns_residual_rk_stage is the same computation as ns_residual followed by
     rk_stage (R rounded to its storage type in both): bitwise equal."""
