@@ -74,7 +74,7 @@ def _p(a: np.ndarray):
 
 # Split forms of the convective term (Sec. 2.3.1 and the inviscid comparison of
 # Sec. 4.2), by the value of Params.split.
-SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4}
+SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4, "kok": 5, "keep": 6}
 
 
 def _blaisdell_only(status, what):

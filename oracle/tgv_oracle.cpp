@@ -30,8 +30,13 @@
 //     Sec. 2.3.1), pairing (rho u_j) x (phi); Jameson, pairing (rho) x (u_j phi);
 //     Kennedy-Gruber-Pirozzoli, the cubic split averaging the divergence form
 //     and all six product-rule expansions of the triple product (weights 1/4);
-//     phi = E is the specific total energy (rho E)/rho;
-//   * pressure terms in divergence form, not split;
+//     phi = E is the specific total energy (rho E)/rho; Kok's form (Kok 2009),
+//     Feiereisen's pairing for mass and momentum, and the kinetic energy and
+//     entropy preserving form KEEP (Kuya, Totani and Kawai 2018), the cubic
+//     split for mass and momentum; both carry the energy as internal plus
+//     kinetic energy and split the pressure work (see residual());
+//   * pressure terms in divergence form, not split (Kok and KEEP: the pressure
+//     gradient in divergence form, the pressure work split);
 //   * constant viscosity mu = 1, Stokes stress, Fourier heat flux with
 //     kappa = 1/((gamma-1) M^2 Pr Re), T = gamma M^2 p / rho (equation of state
 //     consistent with the isothermal initial density of Sec. 4.1);
@@ -54,7 +59,7 @@ struct Params {
   double L[3];
   double gamma, mach, re, pr;
   int viscous;
-  int split;  // 0 Blaisdell, 1 divergence, 2 Feiereisen, 3 Jameson, 4 KGP
+  int split;  // 0 Blaisdell, 1 divergence, 2 Feiereisen, 3 Jameson, 4 KGP, 5 Kok, 6 KEEP
 };
 
 Params unpack(const double* pv) {
@@ -263,7 +268,9 @@ void residual(const Params& P, const S* q, S* r) {
     for (long i = 0; i < N; ++i) phi[4][i] = w.E[i] / w.rho[i];
     Field<S> Drho[3];
     for (int d = 0; d < 3; ++d) Drho[d] = D1(P, w.rho, d);
-    for (int f = 0; f < 5; ++f) {
+    // (Kok and KEEP treat the energy apart, below: the loop stops at m3 for them.)
+    const int nf = P.split >= 5 ? 4 : 5;
+    for (int f = 0; f < nf; ++f) {
       C[f].assign(N, S(0.0));
       for (int d = 0; d < 3; ++d) {
         Field<S> t_div = D1(P, mul(*cons[f], w.u[d]), d);
@@ -277,7 +284,7 @@ void residual(const Params& P, const S* q, S* r) {
           S c;
           if (P.split == 1)
             c = t_div[i];
-          else if (P.split == 2)
+          else if (P.split == 2 || P.split == 5)
             c = 0.5 * (t_div[i] + t_phDm[i] + t_mDph[i]);
           else if (P.split == 3)
             c = 0.5 * (t_div[i] + t_rDuf[i] + t_ufDr[i]);
@@ -288,13 +295,67 @@ void residual(const Params& P, const S* q, S* r) {
       }
     }
   }
+  if (P.split >= 5) {
+    // Kok (split 5) and KEEP (split 6) transport the total energy as internal
+    // energy e = p / ((gamma - 1) rho) plus kinetic energy |u|^2 / 2.  The
+    // internal part takes the pairing of the momentum: Kok's (rho u_d) x (e),
+    // KEEP's cubic rho x u_d x e.  The kinetic part is the split form whose
+    // two-point flux is the mass flux times u_a(left) u_a(right) / 2 (Kok:
+    // mass flux (rho u_d) averaged; KEEP: rho and u_d averaged apart):
+    //   Kok:  1/2 sum_a [ m_d u_a D(u_a) + u_a D(m_d u_a) ]
+    //   KEEP: 1/4 sum_a [ m_d u_a D(u_a) + u_a D(m_d u_a) + m_a D(u_d u_a) + u_d u_a D(m_a) ]
+    // The pressure work is split as p D(u_d) + u_d D(p) (below).
+    Field<S> e(N), rhoe(N);
+    for (long i = 0; i < N; ++i) {
+      rhoe[i] = w.p[i] / (P.gamma - 1.0);
+      e[i] = rhoe[i] / w.rho[i];
+    }
+    C[4].assign(N, S(0.0));
+    for (int d = 0; d < 3; ++d) {
+      Field<S> t_div = D1(P, mul(w.m[d], e), d);   // D(rho u_d e)
+      Field<S> t_eDm = mul(e, D1(P, w.m[d], d));    // e D(m_d)
+      Field<S> t_mDe = mul(w.m[d], D1(P, e, d));    // m_d D(e)
+      Field<S> internal(N);
+      if (P.split == 5) {
+        for (long i = 0; i < N; ++i) internal[i] = 0.5 * (t_div[i] + t_eDm[i] + t_mDe[i]);
+      } else {
+        Field<S> t_rDue = mul(w.rho, D1(P, mul(w.u[d], e), d));          // rho D(u_d e)
+        Field<S> t_uDre = mul(w.u[d], D1(P, rhoe, d));                    // u_d D(rho e)
+        Field<S> t_reDu = mul(rhoe, Du[d]);                               // rho e D(u_d)
+        Field<S> t_ueDr = mul(mul(w.u[d], e), D1(P, w.rho, d));          // u_d e D(rho)
+        for (long i = 0; i < N; ++i)
+          internal[i] = 0.25 * (t_div[i] + t_rDue[i] + t_uDre[i] + t_eDm[i] + t_mDe[i] + t_reDu[i] + t_ueDr[i]);
+      }
+      add(C[4], internal);
+      for (int a = 0; a < 3; ++a) {
+        Field<S> mu = mul(w.m[d], w.u[a]);                      // m_d u_a
+        Field<S> k1 = mul(mu, D1(P, w.u[a], d));                // m_d u_a D(u_a)
+        Field<S> k2 = mul(w.u[a], D1(P, mu, d));                // u_a D(m_d u_a)
+        if (P.split == 5) {
+          for (long i = 0; i < N; ++i) C[4][i] += 0.5 * (k1[i] + k2[i]);
+        } else {
+          Field<S> k3 = mul(w.m[a], D1(P, mul(w.u[d], w.u[a]), d));   // m_a D(u_d u_a)
+          Field<S> k4 = mul(mul(w.u[d], w.u[a]), D1(P, w.m[a], d));   // u_d u_a D(m_a)
+          for (long i = 0; i < N; ++i) C[4][i] += 0.25 * (k1[i] + k2[i] + k3[i] + k4[i]);
+        }
+      }
+    }
+  }
 
   // Pressure: P_rho = 0, P_{m_a} = D_a p, P_E = sum_d D_d(p u_d).
   Field<S> Pr[5];
   Pr[0].assign(N, S(0.0));
   for (int a = 0; a < 3; ++a) Pr[a + 1] = D1(P, w.p, a);
   Pr[4].assign(N, S(0.0));
-  for (int d = 0; d < 3; ++d) add(Pr[4], D1(P, mul(w.p, w.u[d]), d));
+  for (int d = 0; d < 3; ++d) {
+    if (P.split >= 5) {
+      // Kok and KEEP: pressure work split as p D(u_d) + u_d D(p)
+      add(Pr[4], mul(w.p, Du[d]));
+      add(Pr[4], mul(w.u[d], D1(P, w.p, d)));
+    } else {
+      add(Pr[4], D1(P, mul(w.p, w.u[d]), d));
+    }
+  }
 
   // Viscous and heat-flux terms.
   Field<S> V[5];
@@ -681,7 +742,8 @@ struct PointEval {
     auto phi = [this](int f, int x, int y, int z) {
       return f == 0 ? 1.0 : f < 4 ? vel(f - 1, x, y, z) : cons(4, x, y, z) / cons(0, x, y, z);
     };
-    for (int f = 0; f < 5; ++f) {
+    const int nf = P.split >= 5 ? 4 : 5;  // Kok and KEEP: energy below
+    for (int f = 0; f < nf; ++f) {
       double C = 0.0;
       for (int d = 0; d < 3; ++d) {
         auto qu = [&, f, d](int x, int y, int z) { return cons(f, x, y, z) * vel(d, x, y, z); };
@@ -703,7 +765,7 @@ struct PointEval {
         const double t_ufDr = u[d] * ph0 * d1(Qf(0), d, i, j, k);
         if (P.split == 1)
           C += t_div;
-        else if (P.split == 2)
+        else if (P.split == 2 || P.split == 5)
           C += 0.5 * (t_div + t_phDm + t_mDph);
         else if (P.split == 3)
           C += 0.5 * (t_div + t_rDuf + t_ufDr);
@@ -712,8 +774,44 @@ struct PointEval {
       }
       out[f] -= C;
     }
+    if (P.split >= 5) {
+      // Kok / KEEP energy: internal energy e = p/((gamma-1) rho) by the
+      // momentum's pairing, kinetic energy by the split of the two-point flux
+      // (mass flux) u_a(left) u_a(right)/2, pressure work p D u_d + u_d D p.
+      auto eint = [this](int x, int y, int z) { return pres(x, y, z) / ((P.gamma - 1.0) * cons(0, x, y, z)); };
+      const double e0 = eint(i, j, k), rho0 = cons(0, i, j, k);
+      double C = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        auto me = [&, d](int x, int y, int z) { return cons(d + 1, x, y, z) * eint(x, y, z); };
+        const double md = cons(d + 1, i, j, k);
+        const double Dm = d1(Qf(d + 1), d, i, j, k), De = d1(eint, d, i, j, k);
+        if (P.split == 5) {
+          C += 0.5 * (d1(me, d, i, j, k) + e0 * Dm + md * De);
+        } else {
+          auto ue = [&, d](int x, int y, int z) { return vel(d, x, y, z) * eint(x, y, z); };
+          auto re = [&](int x, int y, int z) { return pres(x, y, z) / (P.gamma - 1.0); };
+          C += 0.25 * (d1(me, d, i, j, k) + rho0 * d1(ue, d, i, j, k) + u[d] * d1(re, d, i, j, k) + e0 * Dm +
+                       md * De + rho0 * e0 * d1(U(d), d, i, j, k) + u[d] * e0 * d1(Qf(0), d, i, j, k));
+        }
+        for (int a = 0; a < 3; ++a) {
+          auto mu = [&, d, a](int x, int y, int z) { return cons(d + 1, x, y, z) * vel(a, x, y, z); };
+          const double kin = md * u[a] * d1(U(a), d, i, j, k) + u[a] * d1(mu, d, i, j, k);
+          if (P.split == 5) {
+            C += 0.5 * kin;
+          } else {
+            auto uu = [&, d, a](int x, int y, int z) { return vel(d, x, y, z) * vel(a, x, y, z); };
+            C += 0.25 * (kin + cons(a + 1, i, j, k) * d1(uu, d, i, j, k) + u[d] * u[a] * d1(Qf(a + 1), d, i, j, k));
+          }
+        }
+      }
+      out[4] -= C;
+    }
     for (int a = 0; a < 3; ++a) out[a + 1] -= d1(Pf, a, i, j, k);
     for (int d = 0; d < 3; ++d) {
+      if (P.split >= 5) {
+        out[4] -= pres(i, j, k) * d1(U(d), d, i, j, k) + u[d] * d1(Pf, d, i, j, k);
+        continue;
+      }
       auto pu = [&, d](int x, int y, int z) { return pres(x, y, z) * vel(d, x, y, z); };
       out[4] -= d1(pu, d, i, j, k);
     }

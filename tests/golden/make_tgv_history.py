@@ -28,8 +28,7 @@ def sample_indices(N):
     return np.sort(np.random.default_rng(SAMPLE_SEED).choice(N, 512, replace=False)).astype(np.int64)
 
 
-def write(n, dt, steps, every, wall, hist, idx, qs):
-    out = os.path.join(HERE, f"tgv{n}_dp_trajectory.txt")
+def write(out, n, dt, steps, every, wall, hist, idx, qs):
     with open(out + ".tmp", "w") as fh:
         fh.write(f"# FP64 oracle, Taylor-Green vortex {n}^3 (Sec. 4.1 initial state, Re 1600, M 0.1, Pr 0.71,\n")
         fh.write(f"# gamma 1.4, (2 pi)^3), 4th-order scheme, RK3 (Sec. 3.1), dt {dt!r}, {steps} steps.\n")
@@ -51,10 +50,12 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--every", type=int, default=10)
     ap.add_argument("--chunk", type=int, default=20)
+    ap.add_argument("--out", default=None, help="output file (default: tgv<n>_dp_trajectory.txt beside this script)")
     a = ap.parse_args()
     n = a.n
     assert a.chunk % a.every == 0, "--chunk must be a multiple of --every"
     dt = 3.7e-3 * 32 / n  # constant CFL
+    out = a.out or os.path.join(HERE, f"tgv{n}_dp_trajectory.txt")
     p = O.Params(n=(n, n, n))
     idx = sample_indices(p.N)
     t = time.time()
@@ -64,10 +65,9 @@ def main():
         q, h = O.run(p, dt, k, q, every=a.every)
         hist = h if hist is None else np.concatenate([hist, h[1:]])
         done += k
-        write(n, dt, done, a.every, time.time() - t, hist, idx, q.reshape(5, -1)[:, idx].T)
+        write(out, n, dt, done, a.every, time.time() - t, hist, idx, q.reshape(5, -1)[:, idx].T)
         print("steps", done, "of", a.steps, "after", round(time.time() - t), "s", flush=True)
     wall = time.time() - t
-    out = os.path.join(HERE, f"tgv{n}_dp_trajectory.txt")
     print("wrote", out, "in", wall, "s")
 
 

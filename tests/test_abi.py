@@ -49,7 +49,8 @@ def test_rejects_grids_below_stencil_width(n):
 
 def test_rejects_unsupported_precision_forms():
     bad = [tgv.Prec(tgv.f16, tgv.f64, tgv.f64, tgv.f64), tgv.Prec(tgv.f64, tgv.f64, tgv.f64, tgv.f16),
-           tgv.Prec(tgv.f32, tgv.f32, tgv.f32, tgv.f16), tgv.Prec(tgv.bf16, tgv.bf16, tgv.bf16, tgv.f32)]
+           tgv.Prec(tgv.f32, tgv.f32, tgv.f32, tgv.bf16), tgv.Prec(tgv.bf16, tgv.bf16, tgv.bf16, tgv.f32),
+           tgv.Prec(tgv.f64, tgv.f64, tgv.f16, tgv.f16), tgv.Prec(tgv.f64, tgv.f32, tgv.f32, tgv.f32)]
     for prec in bad:
         assert _call_residual(tgv.Params(n=(8, 8, 8)), prec) == NS_ERR_DTYPE
         assert "unsupported precision form" in tgv.ns_last_error()

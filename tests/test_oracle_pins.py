@@ -311,8 +311,8 @@ SPLITS = list(O.SPLIT_FORMS.items())
 @pytest.mark.parametrize("name,split", SPLITS)
 def test_split_form_matches_dense_brute_force(name, split):
     """The brute force builds each form from its pairing of the factors
-    rho, u_j, phi (and KGP from its identity with the three pairings), not from
-    the oracle's term list."""
+    rho, u_j, phi (and KGP from its identity with the three pairings; Kok and
+    KEEP from their two-point fluxes), not from the oracle's term list."""
     p = P((12, 10, 8), split=split)
     for q in (O.init(p), S.random_state(p.n, 31, smooth=True), S.random_state(p.n, 32)):
         for visc in (1, 0):
@@ -321,6 +321,50 @@ def test_split_form_matches_dense_brute_force(name, split):
             rb = brute.residual(q, p.n, p.L, p.gamma, p.mach, p.re, p.pr, bool(visc), name)
             err = np.abs(r - rb).reshape(5, -1).max(axis=1)
             assert np.all(err <= 1e-15 * term_scale(p, q)), (name, err)
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+def test_split_form_matches_two_point_flux_form(name, split):
+    """Every split form written as the conservative difference of interface
+    fluxes assembled from its symmetric two-point flux (Kok 2009; Kuya, Totani
+    and Kawai 2018: {rho phi}{u}, {rho u}{phi}, {rho}{u}{phi}, ..., and for Kok
+    and KEEP the internal-plus-kinetic energy flux with u_a(left) u_a(right)/2
+    and the pressure flux (p_L u_R + p_R u_L)/2).  The oracle codes product-rule
+    expansions instead; the two agree only if each expansion is the exact
+    algebraic image of its flux."""
+    p = P((12, 10, 8), split=split)
+    for q in (O.init(p), S.random_state(p.n, 33, smooth=True), S.random_state(p.n, 34)):
+        for visc in (1, 0):
+            p.viscous = visc
+            r = O.residual(p, q)
+            rb = brute.residual(q, p.n, p.L, p.gamma, p.mach, p.re, p.pr, bool(visc), name, flux_form=True)
+            err = np.abs(r - rb).reshape(5, -1).max(axis=1)
+            assert np.all(err <= 4e-15 * term_scale(p, q)), (name, err / term_scale(p, q))
+
+
+@pytest.mark.parametrize("name,split", SPLITS)
+def test_kinetic_energy_preservation(name, split):
+    """Semi-discrete kinetic energy budget of the inviscid residual:
+    sum_i [u_a R_{m_a} - |u|^2 R_rho / 2] = sum_i p D_a u_a holds exactly (the
+    convective terms neither create nor destroy kinetic energy; only the
+    pressure-dilatation work remains) for the forms built on the (rho u) x u_a
+    or rho x u x u_a pairings with a consistent mass flux -- Feiereisen, KGP,
+    Kok and KEEP -- and fails, by far more than rounding, for the others."""
+    p = P((12, 16, 10), viscous=0, split=split)
+    q = S.random_state(p.n, 51)
+    r = O.residual(p, q)
+    ops = brute.Ops(p.n, p.L)
+    rho = q[0]
+    u = [q[a + 1] / rho for a in range(3)]
+    pr = (p.gamma - 1) * (q[4] - 0.5 * sum(q[a + 1] * u[a] for a in range(3)))
+    ke_rate = sum(u[a] * r[a + 1] for a in range(3)) - 0.5 * sum(uu ** 2 for uu in u) * r[0]
+    work = pr * sum(ops.d1(u[a], a) for a in range(3))
+    scale = np.abs(sum(u[a] * r[a + 1] for a in range(3))).sum() + np.abs(work).sum()
+    gap = abs(ke_rate.sum() - work.sum()) / scale
+    if name in ("feiereisen", "kgp", "kok", "keep"):
+        assert gap <= 1e-15, (name, gap)
+    else:
+        assert gap >= 1e-8, (name, gap)
 
 
 @pytest.mark.parametrize("name,split", SPLITS)
@@ -386,6 +430,13 @@ def test_split_forms_relations():
     comb = 0.5 * (R["blaisdell"] + R["feiereisen"] + R["jameson"]) - 0.5 * R["divergence"]
     for f in range(5):
         assert close(R["kgp"][f], comb[f], f), f
+    # Kok shares Feiereisen's mass and momentum terms, KEEP those of KGP; their
+    # energy terms differ (internal + kinetic energy, split pressure work)
+    for f in range(4):
+        assert close(R["kok"][f], R["feiereisen"][f], f), f
+        assert close(R["keep"][f], R["kgp"][f], f), f
+    for a, b in (("kok", "feiereisen"), ("keep", "kgp"), ("kok", "keep")):
+        assert np.abs(R[a][4] - R[b][4]).max() > 1e-5 * np.abs(R[b][4]).max(), (a, b)
     # and the forms do differ where phi varies (by their truncation errors)
     for a, b in (("feiereisen", "blaisdell"), ("jameson", "blaisdell"), ("divergence", "kgp")):
         assert np.abs(R[a][1] - R[b][1]).max() > 1e-4 * np.abs(R[b][1]).max(), (a, b)
@@ -690,7 +741,7 @@ def test_trajectory_gradient_matches_complex_step():
     assert abs(np.sum(g * delta) - dd) <= 1e-11 * abs(dd), (np.sum(g * delta), dd)
 
 
-@pytest.mark.parametrize("split", [1, 2, 3, 4])
+@pytest.mark.parametrize("split", [1, 2, 3, 4, 5, 6])
 def test_adjoint_refuses_other_split_forms(split):
     """The C routines of the reverse mode are the transpose of the Blaisdell
     residual only; they refuse any other split form themselves (status -1) and
