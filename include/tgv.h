@@ -66,7 +66,17 @@ typedef enum { NS_F64 = 0, NS_F32 = 1, NS_F16 = 2, NS_BF16 = 3 } ns_dtype_t;
  *   JAMESON    (rho) x (u_j phi):  [D(rho u_j phi) + rho D(u_j phi) + u_j phi D(rho)] / 2
  *   KGP        Kennedy-Gruber-Pirozzoli cubic form: the divergence term and
  *              the six product-rule expansions of the triple product, each / 4.
- * The pressure terms stay in divergence form in every variant.  Forms other
+ *   KOK        Kok (2009): FEIEREISEN for mass and momentum; the energy as
+ *              internal energy e = p/((gamma-1) rho) with the (rho u_j) x (e)
+ *              pairing plus kinetic energy split as
+ *              [m_j u_a D(u_a) + u_a D(m_j u_a)] / 2 (two-point flux: mass flux
+ *              times u_a(left) u_a(right) / 2); pressure work p D(u_j) + u_j D(p).
+ *   KEEP       kinetic energy and entropy preserving form (Kuya, Totani and
+ *              Kawai 2018): KGP for mass, momentum and internal energy; kinetic
+ *              energy [m_j u_a D(u_a) + u_a D(m_j u_a) + m_a D(u_j u_a)
+ *              + u_j u_a D(m_a)] / 4; pressure work as KOK.
+ * The pressure gradient stays in divergence form in every variant, and so does
+ * the pressure work except in KOK and KEEP.  Forms other
  * than BLAISDELL are available in the DP and HPSP precision forms, and the
  * adjoint supports BLAISDELL only (NS_ERR_ARG otherwise). */
 typedef enum {
@@ -74,7 +84,9 @@ typedef enum {
   NS_SPLIT_DIVERGENCE = 1,
   NS_SPLIT_FEIEREISEN = 2,
   NS_SPLIT_JAMESON = 3,
-  NS_SPLIT_KGP = 4
+  NS_SPLIT_KGP = 4,
+  NS_SPLIT_KOK = 5,
+  NS_SPLIT_KEEP = 6
 } ns_split_t;
 
 typedef struct {

@@ -77,8 +77,8 @@ int check_params(const ns_params_t* p, tgv::Grid* g) {
   if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) return fail(NS_ERR_ARG, "gamma must be finite and > 1");
   if (!finite_pos(p->mach)) return fail(NS_ERR_ARG, "mach must be finite and > 0");
   if (p->viscous != 0 && p->viscous != 1) return fail(NS_ERR_ARG, "viscous must be 0 or 1");
-  if (p->split < NS_SPLIT_BLAISDELL || p->split > NS_SPLIT_KGP)
-    return fail(NS_ERR_ARG, "split must be one of NS_SPLIT_BLAISDELL .. NS_SPLIT_KGP");
+  if (p->split < NS_SPLIT_BLAISDELL || p->split > NS_SPLIT_KEEP)
+    return fail(NS_ERR_ARG, "split must be one of NS_SPLIT_BLAISDELL .. NS_SPLIT_KEEP");
   if (!finite_pos(p->reynolds)) return fail(NS_ERR_ARG, "reynolds must be finite and > 0");
   if (!finite_pos(p->prandtl)) return fail(NS_ERR_ARG, "prandtl must be finite and > 0");
   g->nx = p->n[0];
@@ -129,6 +129,7 @@ tgv::Coef<Tc> make_coef(const ns_params_t* p) {
     c.c2[d] = (Tc)(1.0 / (12.0 * h * h));
   }
   c.gm1 = (Tc)(p->gamma - 1.0);
+  c.igm1 = (Tc)(1.0 / (p->gamma - 1.0));
   c.gm2 = (Tc)(p->gamma * p->mach * p->mach);
   c.ire = (Tc)(1.0 / p->reynolds);
   const double kap = 1.0 / ((p->gamma - 1.0) * p->mach * p->mach * p->prandtl * p->reynolds);

@@ -205,7 +205,74 @@ struct WinNb {
 // combined as: divergence t_div; Feiereisen (t_div + t_phDm + t_mDph)/2;
 // Jameson (t_div + t_rDuf + t_ufDr)/2; Kennedy-Gruber-Pirozzoli the sum of all
 // seven / 4.  The pressure terms stay in divergence form.
-enum { SPLIT_BLAISDELL = 0, SPLIT_DIVERGENCE = 1, SPLIT_FEIEREISEN = 2, SPLIT_JAMESON = 3, SPLIT_KGP = 4 };
+//
+// Kok's form (Kok 2009) and KEEP (Kuya, Totani and Kawai 2018) take the
+// Feiereisen resp. KGP terms for mass and momentum, and carry the energy as
+// internal energy e = p / ((gamma - 1) rho), transported with the same
+// pairing, plus kinetic energy in the split whose two-point flux is the mass
+// flux times u_a(left) u_a(right) / 2:
+//   Kok:  1/2 sum_a [ m_d u_a D(u_a) + u_a D(m_d u_a) ]
+//   KEEP: 1/4 sum_a [ m_d u_a D(u_a) + u_a D(m_d u_a) + m_a D(u_d u_a) + u_d u_a D(m_a) ]
+// with the pressure work split as p D(u_d) + u_d D(p).
+enum {
+  SPLIT_BLAISDELL = 0,
+  SPLIT_DIVERGENCE = 1,
+  SPLIT_FEIEREISEN = 2,
+  SPLIT_JAMESON = 3,
+  SPLIT_KGP = 4,
+  SPLIT_KOK = 5,
+  SPLIT_KEEP = 6
+};
+
+// Kok / KEEP energy convection and pressure work of direction d (see above).
+template <class Tc, int d, int SPLIT, class Nb>
+__device__ __forceinline__ Tc kinetic_internal_energy(const Nb& nb, const Tc* c0, Tc ir0, const Coef<Tc>& c,
+                                                      const Tc (&ud)[4], const Tc (&rh)[4], const Tc (&md)[4],
+                                                      const Tc (&pn)[4], Tc Dud, Tc Drho, Tc Dmd) {
+  const Tc u0 = c0[F_U + d], r0 = c0[F_RHO], m0 = c0[F_M + d], p0 = c0[F_P];
+  Tc en[4];  // specific internal energy at the neighbours
+#pragma unroll
+  for (int s = 0; s < 4; ++s) en[s] = pn[s] * nb.ir(s) * c.igm1;
+  const Tc e0 = p0 * ir0 * c.igm1;
+  const Tc t_div = S1(md[0] * en[0], md[1] * en[1], md[2] * en[2], md[3] * en[3]);
+  const Tc t_eDm = e0 * Dmd, t_mDe = m0 * S1(en[0], en[1], en[2], en[3]);
+  Tc cv;
+  if constexpr (SPLIT == SPLIT_KOK) {
+    cv = Tc(0.5) * (t_div + t_eDm + t_mDe);
+  } else {
+    const Tc t_rDue = r0 * S1(ud[0] * en[0], ud[1] * en[1], ud[2] * en[2], ud[3] * en[3]);
+    const Tc t_uDre = u0 * c.igm1 * S1(pn[0], pn[1], pn[2], pn[3]);
+    const Tc t_reDu = p0 * c.igm1 * Dud;
+    const Tc t_ueDr = u0 * e0 * Drho;
+    cv = Tc(0.25) * (t_div + t_rDue + t_uDre + t_eDm + t_mDe + t_reDu + t_ueDr);
+  }
+  Tc kin = Tc(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Tc un[4], mu[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      un[s] = (a == d) ? ud[s] : nb(F_U + a, s);
+      mu[s] = md[s] * un[s];
+    }
+    const Tc ua0 = c0[F_U + a];
+    const Tc k12 = m0 * ua0 * S1(un[0], un[1], un[2], un[3]) + ua0 * S1(mu[0], mu[1], mu[2], mu[3]);
+    if constexpr (SPLIT == SPLIT_KOK) {
+      kin += k12;
+    } else {
+      Tc ma[4], uu[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ma[s] = (a == d) ? md[s] : nb(F_M + a, s);
+        uu[s] = ud[s] * un[s];
+      }
+      kin += k12 + c0[F_M + a] * S1(uu[0], uu[1], uu[2], uu[3]) + u0 * ua0 * S1(ma[0], ma[1], ma[2], ma[3]);
+    }
+  }
+  cv += (SPLIT == SPLIT_KOK ? Tc(0.5) : Tc(0.25)) * kin;
+  // pressure work p D(u_d) + u_d D(p)
+  return cv + p0 * Dud + u0 * S1(pn[0], pn[1], pn[2], pn[3]);
+}
 
 template <class Tc, int d, int SPLIT, class Nb>
 __device__ __forceinline__ void split_convection(const Nb& nb, const Tc* c0, Tc ir0, const Coef<Tc>& c,
@@ -223,8 +290,9 @@ __device__ __forceinline__ void split_convection(const Nb& nb, const Tc* c0, Tc 
   const Tc Dud = S1(ud[0], ud[1], ud[2], ud[3]);
   const Tc Drho = S1(rh[0], rh[1], rh[2], rh[3]);
   const Tc Dmd = S1(md[0], md[1], md[2], md[3]);
+  constexpr bool kEnergyApart = SPLIT == SPLIT_KOK || SPLIT == SPLIT_KEEP;
 #pragma unroll
-  for (int f = 0; f < 5; ++f) {
+  for (int f = 0; f < (kEnergyApart ? 4 : 5); ++f) {
     Tc qn[4], ph[4], q0, ph0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -253,7 +321,7 @@ __device__ __forceinline__ void split_convection(const Nb& nb, const Tc* c0, Tc 
     Tc cv;
     if constexpr (SPLIT == SPLIT_DIVERGENCE) {
       cv = t_div;
-    } else if constexpr (SPLIT == SPLIT_FEIEREISEN) {
+    } else if constexpr (SPLIT == SPLIT_FEIEREISEN || SPLIT == SPLIT_KOK) {
       const Tc t_phDm = ph0 * Dmd, t_mDph = m0 * S1(ph[0], ph[1], ph[2], ph[3]);
       cv = Tc(0.5) * (t_div + t_phDm + t_mDph);
     } else if constexpr (SPLIT == SPLIT_JAMESON) {
@@ -271,7 +339,10 @@ __device__ __forceinline__ void split_convection(const Nb& nb, const Tc* c0, Tc 
     R[f] -= sc1 * cv;
   }
   R[1 + d] -= sc1 * S1(pn[0], pn[1], pn[2], pn[3]);
-  R[4] -= sc1 * S1(pn[0] * ud[0], pn[1] * ud[1], pn[2] * ud[2], pn[3] * ud[3]);
+  if constexpr (kEnergyApart)
+    R[4] -= sc1 * kinetic_internal_energy<Tc, d, SPLIT>(nb, c0, ir0, c, ud, rh, md, pn, Dud, Drho, Dmd);
+  else
+    R[4] -= sc1 * S1(pn[0] * ud[0], pn[1] * ud[1], pn[2] * ud[2], pn[3] * ud[3]);
 }
 
 // Convective + pressure + linear viscous terms of direction d at one point:
@@ -1131,6 +1202,7 @@ Coef<h2> splat(const Coef<f16>& c) {
     o.kap2[d] = sp(c.kap2[d]);
   }
   o.gm1 = sp(c.gm1);
+  o.igm1 = sp(c.igm1);
   o.gm2 = sp(c.gm2);
   o.ire = sp(c.ire);
   o.kap = sp(c.kap);
@@ -1212,6 +1284,8 @@ hipError_t launch_split(int split, const Grid& g, const Coef<Tc>& c, const void*
       case SPLIT_FEIEREISEN: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_FEIEREISEN>(g, c, q, r, rk, st);
       case SPLIT_JAMESON: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_JAMESON>(g, c, q, r, rk, st);
       case SPLIT_KGP: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_KGP>(g, c, q, r, rk, st);
+      case SPLIT_KOK: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_KOK>(g, c, q, r, rk, st);
+      case SPLIT_KEEP: return launch_tiled<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT_KEEP>(g, c, q, r, rk, st);
       default: break;
     }
   }

@@ -233,6 +233,7 @@ struct Coef {
   Tc c1[3];   // 1 / (12 h_d): first-derivative scale
   Tc c2[3];   // 1 / (12 h_d^2): second-derivative scale
   Tc gm1;     // gamma - 1
+  Tc igm1;    // 1 / (gamma - 1)
   Tc gm2;     // gamma M^2
   Tc ire;     // 1 / Re
   Tc kap;     // 1 / ((gamma - 1) M^2 Pr Re)

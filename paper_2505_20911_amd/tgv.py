@@ -91,7 +91,8 @@ def load():
 
 
 # Split forms of the convective term (ns_split_t).
-SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4}
+SPLIT_FORMS = {"blaisdell": 0, "divergence": 1, "feiereisen": 2, "jameson": 3, "kgp": 4, "kok": 5,
+               "keep": 6}
 
 
 @dataclass(frozen=True)

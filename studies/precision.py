@@ -10,7 +10,7 @@ C-ABI) and measures, against the FP64 oracle trajectory computed on the host:
     difference of eps^S from the double-precision run over the samples.
 It also times each form (Mpt.stage/s) so speedups can be read beside errors.
 
-Usage (GPU): python tests/precision_study.py --n 64 --steps 200 --every 10
+Usage (GPU): python studies/precision.py --n 64 --steps 200 --every 10
 The oracle reference is feasible up to ~64^3 x a few hundred steps on the
 host; with --reference dp the GPU FP64 path (validated against the oracle at
 smaller sizes and on sampled points at full size) is the reference instead.
@@ -27,7 +27,8 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-FORMS = ["DP", "SPDP_C64", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HP"]
+FORMS = ["DP", "SPDP_C64", "SPDP_WK", "SPDP", "SP_DPC", "SP", "HPSP", "HPSP_BF16", "HPSP_WK", "HPSP_RESWK", "HP",
+         "HP_C16"]
 
 
 def run_form(form, n, dt, nsteps, every, mach=0.1, reynolds=1600.0):

@@ -7,7 +7,7 @@ grow and diverge.  Reports, per form and precision, K/K0 at the end (or where
 the run stopped) and the first time K/K0 leaves [0.5, 1.5] or turns
 non-finite.
 
-Usage (GPU): python tests/split_form_study.py [--n 64] [--steps 5000] > split.json
+Usage (GPU): python studies/split_forms.py [--n 64] [--steps 5000] > split.json
 """
 import argparse
 import json
