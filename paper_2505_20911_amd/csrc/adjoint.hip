@@ -5,19 +5,18 @@
 // D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
 // stencil term of the forward residual turns into a stencil of R_bar-weighted
 // pointwise fields evaluated around the output point, plus pointwise terms.
-// Three passes over a caller-provided workspace of 18 fields:
-//   pass 0 (pointwise, viscous only) stores what pass A reads at stencil
-//     neighbours: u_a and V_bar_a = R_bar_{m_a} + R_bar_E u_a;
-//   pass A (viscous only) stores the adjoint of the viscous work sum
-//     tau_ad G_ad, the symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components),
-//     and the inner derivatives of the mixed second-derivative terms,
-//     sigma_a = sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a, so
-//     that D_a D_b u_b and (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one
-//     more first difference each in pass B (D_a and D_b commute on the
-//     periodic grid);
-//   pass B gathers every transposed-stencil and pointwise contribution,
-//     re-deriving u_a, V_bar_a and sum_f R_bar_f Q_f at each neighbour from Q
-//     and R_bar (which it loads there anyway) rather than reading them back.
+// Passes, each a z-march over LDS-staged planes (plane_march_kernel):
+//   pass B gathers every transposed-stencil and pointwise contribution that
+//     needs only Q and R_bar, re-deriving u_a, V_bar_a = R_bar_{m_a} +
+//     R_bar_E u_a and sum_f R_bar_f Q_f at each neighbour;
+//   for the viscous residual, pass A stores in a caller-provided workspace
+//     of 12 fields the adjoint of the viscous work sum tau_ad G_ad, the
+//     symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components), and the inner
+//     derivatives of the mixed second-derivative terms, sigma_a =
+//     sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a, so that
+//     D_a D_b u_b and (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one more
+//     first difference each in pass C (D_a and D_b commute on the periodic
+//     grid); pass C gathers those workspace terms.
 // 1/rho is the hardware reciprocal refined by Newton-Raphson, as in the
 // forward residual.
 #include "tgv_device.h"
@@ -108,65 +107,216 @@ __device__ __forceinline__ int sym(int a, int d) {
   return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
 }
 
-// Workspace layout, fields of N values each.
-enum { W_U = 0, W_VB = 3, W_GB = 6, W_SIG = 12, W_TAU = 15, W_FIELDS = 18 };
+// Workspace layout (viscous residual only), fields of N values each: the
+// symmetric G_bar_ad = 2 R_bar_E tau_ad and the inner first differences
+// sigma_a = sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a of the
+// mixed second-derivative terms.
+enum { W_GB = 0, W_SIG = 6, W_TAU = 9, W_FIELDS = 12 };
 static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 
-// Pass 0: pointwise fields read at stencil neighbours by pass A.
-template <class T>
-__global__ void __launch_bounds__(kThreads) adj_prim(Grid g, const T* __restrict__ q, const T* __restrict__ rb,
-                                                     T* __restrict__ w) {
-  const long long N = g.N;
-  for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < N;
-       id += (long long)gridDim.x * blockDim.x) {
-  T q0[5], r0[5];
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    q0[f] = q[f * N + id];
-    r0[f] = rb[f * N + id];
+// ---------------------------------------------------------------------------
+// Plane march.  A block owns a GTX x GTY tile of (x, y) columns and marches
+// along z over a chunk of planes.  Each plane of the operator's fields on the
+// tile plus a 2-point halo is staged in LDS, which keeps the three newest
+// planes: the x- and y-neighbours of the output plane c come from its LDS
+// copy, the z-neighbours c + 1, c + 2 from the own column of the next two LDS
+// planes, and c - 1, c - 2 from registers (the own column's values, saved as
+// the planes leave LDS).  Every value is loaded from global memory once per
+// block (plus the halo), where gathering each stencil neighbour from global
+// memory re-read it many times through the caches.  The next plane is
+// requested before the current plane's arithmetic.  An operator supplies NL
+// values loaded per point (load), the NF fields staged from them (derive), and
+// the output of one point (emit).
+// ---------------------------------------------------------------------------
+constexpr int GTX = 32, GTY = 8, GNT = GTX * GTY;
+constexpr int GHX = GTX + 4, GHY = GTY + 4, GNP = GHX * GHY;
+constexpr int GSLOTS = 3;  // LDS planes c, c + 1, c + 2
+constexpr int GLOADS = (GNP + GNT - 1) / GNT;
+
+struct PlaneMarch {
+  int tiles_x, tiles_y, kz;
+  long long blocks;
+};
+
+// Planes per block: long marches amortise the 4 halo planes at the ends of a
+// chunk; the grid keeps at least 1024 blocks where it can.
+PlaneMarch plane_march(const Grid& g) {
+  PlaneMarch m;
+  m.tiles_x = (g.nx + GTX - 1) / GTX;
+  m.tiles_y = (g.ny + GTY - 1) / GTY;
+  m.kz = 128;
+  while (m.kz > 4 && (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz) < 1024) m.kz /= 2;
+  m.blocks = (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz);
+  return m;
+}
+
+// Neighbour accessors handed to an operator's emit: field f at offset index
+// s (0..3 = -2, -1, +1, +2 points) along x and y from the LDS plane of the
+// output plane, along z from the registers and the next two LDS planes.
+template <class T, int NF>
+struct Nbrs {
+  const T* Pc;
+  const T* P1;
+  const T* P2;
+  const T* wm1;
+  const T* wm2;
+  int own;
+  __device__ __forceinline__ T c(int f) const { return Pc[f * GNP + own]; }
+  template <int d>
+  __device__ __forceinline__ T at(int f, int s) const {
+    if constexpr (d == 2) {
+      return s == 0 ? wm2[f] : s == 1 ? wm1[f] : s == 2 ? P1[f * GNP + own] : P2[f * GNP + own];
+    } else {
+      constexpr int st = d == 0 ? 1 : GHX;
+      const int o = (s < 2) ? (s - 2) : (s - 1);
+      return Pc[f * GNP + own + o * st];
+    }
   }
-  const T ir = recip(q0[0]);
+};
+
+template <class T, class Op>
+__global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid g, PlaneMarch pm, int remap, Op op) {
+  constexpr int NF = Op::NF, NL = Op::NL;
+  __shared__ T lds[GSLOTS][NF * GNP];
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
+  const int x0 = (b % pm.tiles_x) * GTX;
+  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
+  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  const int z1 = min(z0 + pm.kz, g.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % GTX, ly = tid / GTX;
+  const int cx = x0 + lx, cy = y0 + ly;
+  const bool valid = cx < g.nx && cy < g.ny;
+  const long long col_off = (long long)cy * g.nx + cx;
+  const int own = (ly + 2) * GHX + (lx + 2);
+
+  // the halo-plane points this thread stages
+  long long off[GLOADS];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T u = q0[a + 1] * ir;
-    w[(W_U + a) * N + id] = u;
-    w[(W_VB + a) * N + id] = r0[a + 1] + r0[4] * u;
+  for (int l = 0; l < GLOADS; ++l) {
+    const int s = tid + l * GNT;
+    const int hx = s % GHX, hy = s / GHX;
+    int x = (x0 - 2 + hx) % g.nx;
+    x += (x < 0) ? g.nx : 0;
+    int y = (y0 - 2 + hy) % g.ny;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
   }
+  auto zoff = [&](int z) {
+    z += (z < 0) ? g.nz : 0;
+    z -= (z >= g.nz) ? g.nz : 0;
+    return (long long)z * g.plane;
+  };
+  T pre[GLOADS][NL];
+  auto fetch = [&](int z) {
+    const long long zo = zoff(z);
+#pragma unroll
+    for (int l = 0; l < GLOADS; ++l)
+      if (tid + l * GNT < GNP) op.load(zo + off[l], pre[l]);
+  };
+  auto stash = [&](int z) {
+    T* P = lds[(z - z0 + 3) % GSLOTS];
+#pragma unroll
+    for (int l = 0; l < GLOADS; ++l) {
+      const int s = tid + l * GNT;
+      if (s < GNP) {
+        T v[NF];
+        op.derive(pre[l], v);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P[f * GNP + s] = v[f];
+      }
+    }
+  };
+  // own-column fields of planes c - 2 and c - 1
+  T wm2[NF], wm1[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) wm2[f] = wm1[f] = T(0);
+  if (valid) {
+    T raw[NL];
+    op.load(zoff(z0 - 2) + col_off, raw);
+    op.derive(raw, wm2);
+    op.load(zoff(z0 - 1) + col_off, raw);
+    op.derive(raw, wm1);
+  }
+  // planes z0 and z0 + 1 into LDS, z0 + 2 requested
+  fetch(z0);
+  stash(z0);
+  fetch(z0 + 1);
+  stash(z0 + 1);
+  fetch(z0 + 2);
+
+#pragma nounroll
+  for (int cz = z0; cz < z1; ++cz) {
+    stash(cz + 2);
+    __syncthreads();
+    if (cz + 3 <= z1 + 1) fetch(cz + 3);
+    const T* Pc = lds[(cz - z0 + 3) % GSLOTS];
+    if (valid) {
+      const Nbrs<T, NF> nbr{Pc, lds[(cz + 1 - z0 + 3) % GSLOTS], lds[(cz + 2 - z0 + 3) % GSLOTS], wm1, wm2, own};
+      op.emit(nbr, zoff(cz) + col_off);
+    }
+    // the own column of plane c moves to the registers before its slot is
+    // overwritten by plane c + 3
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      wm2[f] = wm1[f];
+      wm1[f] = Pc[f * GNP + own];
+    }
+    __syncthreads();
   }
 }
 
-// Pass A: G_bar_ad = 2 R_bar_E tau_ad, sigma_a and tau_b at every point.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_stress(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ rb,
-                                                       T* __restrict__ w) {
-  const Column col = column(g, cm);
-  if (!col.valid) return;
-#pragma nounroll
-  for (int z = col.z0; z < col.z1; ++z) {
-    const int ijk[3] = {col.x, col.y, z};
-    const long long id = (long long)z * g.plane + col.xy;
+__device__ __forceinline__ T first_diff(T m2, T m1, T p1, T p2, T s) {
+  return s * (T(8) * (p1 - m1) - (p2 - m2));
+}
+
+// ---------------------------------------------------------------------------
+// Pass A (viscous only): G_bar_ad, sigma_a and tau_b at every point, from the
+// velocity u_a = m_a / rho and V_bar_a = R_bar_{m_a} + R_bar_E u_a, derived
+// once per point as it is staged.
+// ---------------------------------------------------------------------------
+template <class T>
+struct StressOp {
+  static constexpr int NL = 8, NF = 7, kWavesPerEU = 2;  // (rho, m, R_bar_m, R_bar_E) -> (u, V_bar, R_bar_E)
+  Grid g;
+  Coef<T> c;
+  const T* __restrict__ q;
+  const T* __restrict__ rb;
+  T* __restrict__ w;
+  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[f] = q[f * g.N + i];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[4 + f] = rb[(f + 1) * g.N + i];
+  }
+  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
+    const T ir = recip(v[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T u = v[a + 1] * ir;
+      o[a] = u;
+      o[3 + a] = v[4 + a] + v[7] * u;
+    }
+    o[6] = v[7];
+  }
+  template <int d>
+  __device__ __forceinline__ T D(const Nbrs<T, NF>& n, int f) const {
+    return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
+                      c.c1[d]);
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
     const long long N = g.N;
     T G[3][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      T u[4][3];
-      const int offs[4] = {-2, -1, 1, 2};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const long long n = nb(g, id, ijk, d, offs[s]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) u[s][a] = w[(W_U + a) * N + n];
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
-    }
-    T dv[3];  // D_a V_bar_a
-#pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const long long base = (long long)(W_VB + a) * N;
-      dv[a] = D1(w[base + nb(g, id, ijk, a, -2)], w[base + nb(g, id, ijk, a, -1)], w[base + nb(g, id, ijk, a, 1)],
-                 w[base + nb(g, id, ijk, a, 2)], c.c1[a]);
+      G[a][0] = D<0>(n, a);
+      G[a][1] = D<1>(n, a);
+      G[a][2] = D<2>(n, a);
     }
+    const T dv[3] = {D<0>(n, 3), D<1>(n, 4), D<2>(n, 5)};  // D_a V_bar_a
     w[(W_SIG + 0) * N + id] = G[1][1] + G[2][2];
     w[(W_SIG + 1) * N + id] = G[0][0] + G[2][2];
     w[(W_SIG + 2) * N + id] = G[0][0] + G[1][1];
@@ -174,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) adj_stress(Grid g, ColMarch cm, Coef
     w[(W_TAU + 1) * N + id] = dv[0] + dv[2];
     w[(W_TAU + 2) * N + id] = dv[0] + dv[1];
     const T div = G[0][0] + G[1][1] + G[2][2];
-    const T two_rE = T(2) * rb[4 * N + id];
+    const T two_rE = T(2) * n.c(6);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -183,44 +333,22 @@ __global__ void __launch_bounds__(kThreads) adj_stress(Grid g, ColMarch cm, Coef
         w[(W_GB + sym(a, d)) * N + id] = two_rE * tau;
       }
   }
-}
+};
 
-// Pass B: gather of all transposed-stencil and pointwise contributions.
-// Along each direction the neighbours are visited in symmetric pairs, (-1, +1)
-// and then (-2, +2).  At each neighbour u_a, V_bar_a and sum_f R_bar_f Q_f are
-// derived from Q and R_bar with the expressions pass 0 uses, and every first
-// and second difference is accumulated pair by pair,
+// ---------------------------------------------------------------------------
+// Pass B: the transposed-stencil and pointwise contributions, everything
+// except the viscous-work and mixed-derivative terms that read the workspace
+// (pass C).  Along each direction the neighbours are visited in symmetric
+// pairs, (-1, +1) and then (-2, +2).  At each neighbour u_a, V_bar_a and
+// sum_f R_bar_f Q_f are derived from Q, R_bar and 1/rho, and every first and
+// second difference is accumulated pair by pair,
 //   8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2}),
 //   16 ((f_{+1} - f_0) + (f_{-1} - f_0)) - ((f_{+2} - f_0) + (f_{-2} - f_0))
 // (the factors 8 and 16 are exact), the neighbour differences always taken
-// first.  Only the viscous fields G_bar, sigma and tau come from the
-// workspace.
-// The values of Q and R_bar at one neighbour and what is derived from them.
-template <class T>
-struct NbVals {
-  T q[5], r[5], u[3], vb[3], srq;
-};
-
-template <class T>
-__device__ __forceinline__ void load_nb(const T* __restrict__ q, const T* __restrict__ rb, long long N, long long n,
-                                        NbVals<T>& v) {
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    v.q[f] = q[f * N + n];
-    v.r[f] = rb[f * N + n];
-  }
-  const T ir = recip(v.q[0]);
-  T srq = 0;
-#pragma unroll
-  for (int f = 0; f < 5; ++f) srq += v.r[f] * v.q[f];
-  v.srq = srq;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T u = v.q[a + 1] * ir;
-    v.u[a] = u;
-    v.vb[a] = v.r[a + 1] + v.r[4] * u;
-  }
-}
+// first.  One block of 256 threads per CU in FP64 (its LDS ring is 114 KB),
+// so each wave may use up to 512 registers.
+// ---------------------------------------------------------------------------
+enum { G_Q = 0, G_R = 5, G_IR = 10 };
 
 // Difference sums of one direction (before the 1/(12 h) or 1/(12 h^2) factor).
 // `ubs` collects the terms that enter u_bar_d through a first difference:
@@ -228,7 +356,7 @@ __device__ __forceinline__ void load_nb(const T* __restrict__ q, const T* __rest
 // from the neighbour values first.
 template <class T>
 struct DirSums {
-  T r[5], rud[5], ud, ubs, rE2, vb2[3], u2[3], gb[3], sig, tau;
+  T r[5], rud[5], ud, ubs, rE2, vb2[3], u2[3];
 };
 
 template <int K, class T>
@@ -247,167 +375,244 @@ __device__ __forceinline__ void d2_add(T& acc, T plus, T minus, T c0) {
     acc = acc - sum;
 }
 
-// Pair K of direction d: neighbours at -K and +K.
-template <int K, class T>
-__device__ __forceinline__ void add_pair(DirSums<T>& S, const T* __restrict__ q, const T* __restrict__ rb,
-                                         const T* __restrict__ w, long long N, long long nm, long long np, int d,
-                                         bool viscous, const T (&r0)[5], const T (&vb0)[3], const T (&u0)[3]) {
-  {
-    NbVals<T> m, p;
-    load_nb(q, rb, N, nm, m);
-    load_nb(q, rb, N, np, p);
-    const T udm = d == 0 ? m.u[0] : (d == 1 ? m.u[1] : m.u[2]);
-    const T udp = d == 0 ? p.u[0] : (d == 1 ? p.u[1] : p.u[2]);
-    T ubs = p.srq - m.srq;
+// Pair K of direction d: neighbours m at -K and p at +K, whose fields
+// (q, R_bar, 1/rho in the G_* order) the accessors M(f) and P(f) read; u_a,
+// V_bar_a = R_bar_{m_a} + R_bar_E u_a and sum_f R_bar_f Q_f are derived there.
+// Values are read field by field, so that few are live at once.
+template <int K, int d, class T, class FM, class FP>
+__device__ __forceinline__ void add_pair(DirSums<T>& S, FM M, FP P, bool viscous, const T (&r0)[5],
+                                         const T (&vb0)[3], const T (&u0)[3]) {
+  const T irm = M(G_IR), irp = P(G_IR);
+  T um[3], up[3];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      d1_add<K>(S.r[f], p.r[f] - m.r[f]);
-      const T pu = p.r[f] * udp;
-      const T mu = m.r[f] * udm;
-      d1_add<K>(S.rud[f], pu - mu);
-      ubs -= r0[f] * (p.q[f] - m.q[f]);
-    }
-    d1_add<K>(S.ud, udp - udm);
-    d1_add<K>(S.ubs, ubs);
-    if (viscous) {
-      d2_add<K>(S.rE2, p.r[4], m.r[4], r0[4]);
+  for (int a = 0; a < 3; ++a) {
+    um[a] = M(G_Q + 1 + a) * irm;
+    up[a] = P(G_Q + 1 + a) * irp;
+  }
+  const T udm = um[d], udp = up[d];
+  T srqm = 0, srqp = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        d2_add<K>(S.vb2[a], p.vb[a], m.vb[a], vb0[a]);
-        d2_add<K>(S.u2[a], p.u[a], m.u[a], u0[a]);
-      }
+  for (int f = 0; f < 5; ++f) {
+    const T rm = M(G_R + f), rp = P(G_R + f);
+    srqm += rm * M(G_Q + f);
+    srqp += rp * P(G_Q + f);
+    d1_add<K>(S.r[f], rp - rm);
+    const T pu = rp * udp;
+    const T mu = rm * udm;
+    d1_add<K>(S.rud[f], pu - mu);
+  }
+  T ubs = srqp - srqm;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) ubs -= r0[f] * (P(G_Q + f) - M(G_Q + f));
+  d1_add<K>(S.ud, udp - udm);
+  d1_add<K>(S.ubs, ubs);
+  if (viscous) {
+    const T r4m = M(G_R + 4), r4p = P(G_R + 4);
+    d2_add<K>(S.rE2, r4p, r4m, r0[4]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d2_add<K>(S.vb2[a], P(G_R + 1 + a) + r4p * up[a], M(G_R + 1 + a) + r4m * um[a], vb0[a]);
+      d2_add<K>(S.u2[a], up[a], um[a], u0[a]);
     }
   }
+}
+
+// Centre values of the output point and the accumulators of its adjoint.
+template <class T>
+struct Centre {
+  T q0[5], r0[5], ir0, u0[3], vb0[3], p0, T0;
+  T qb[5], ub[3], pb, Tb, lap[3], X[3];
+};
+
+// Direction d's contributions from its difference sums (terms numbered as
+// in the forward residual: (1)-(3) split convection, (4) pressure gradient,
+// (5) pressure work, (6) viscous momentum D2 parts, (8) heat flux).
+template <int d, class T>
+__device__ __forceinline__ void direction_adjoint(const DirSums<T>& S, bool viscous, const Coef<T>& c,
+                                                  Centre<T>& C) {
+  const T half = T(0.5);
+  const T u0d = C.u0[d];
+  const T s1 = c.c1[d], s2 = c.c2[d];
+  T ubd = 0, Xd = 0;  // contributions to ub[d], X[d]
+  const T dud = s1 * S.ud;  // forward D_d u_d at this point
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const T Dr = s1 * S.r[f];
+    // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
+    const T F = half * Dr;
+    C.qb[f] += F * u0d;
+    ubd += F * C.q0[f];
+    // (2) u_d D_d q_f
+    C.qb[f] += half * (s1 * S.rud[f]);
+    // (3) q_f D_d u_d, pointwise part
+    C.qb[f] -= half * C.r0[f] * dud;
+    // (4) momentum pressure gradient D_d p
+    if (f == d + 1) C.pb += Dr;
+    if (f == 4) {
+      // (5) pressure work D_d(p u_d)
+      C.pb += Dr * u0d;
+      ubd += Dr * C.p0;
+      // (8) heat flux
+      if (viscous) C.Tb += c.kap * (s2 * S.rE2);
+    }
+  }
+  // (2) -R_bar_f D_d q_f and (3) q_f D_d u_d, stencil part summed over f
+  ubd += half * (s1 * S.ubs);
   if (viscous) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T* base = w + (W_GB + sym(a, d)) * N;
-      d1_add<K>(S.gb[a], base[np] - base[nm]);
+      // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
+      const T vb = s2 * S.vb2[a];
+      C.ub[a] += c.ire * vb;
+      if (a == d) ubd += c.ire * (T(1.0 / 3.0)) * vb;
+      // forward pieces of V_{m_a} at this point
+      const T l = s2 * S.u2[a];
+      C.lap[a] += l;
+      if (a == d) Xd += l;
     }
-    d1_add<K>(S.sig, w[(W_SIG + d) * N + np] - w[(W_SIG + d) * N + nm]);
-    d1_add<K>(S.tau, w[(W_TAU + d) * N + np] - w[(W_TAU + d) * N + nm]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    C.ub[a] += a == d ? ubd : T(0);
+    C.X[a] += a == d ? Xd : T(0);
   }
 }
 
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_gather(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ q,
-                                                       const T* __restrict__ rb, const T* __restrict__ w,
-                                                       T* __restrict__ qbar) {
-  const Column col = column(g, cm);
-  if (!col.valid) return;
-  const bool viscous = c.viscous != 0;
-#pragma nounroll
-  for (int z = col.z0; z < col.z1; ++z) {
-    const int ijk[3] = {col.x, col.y, z};
-    const long long id = (long long)z * g.plane + col.xy;
-    const long long N = g.N;
-    const T half = T(0.5);
-
-    T q0[5], r0[5];
+struct GatherOp {
+  static constexpr int NL = 10, NF = 11, kWavesPerEU = 1;  // (q, R_bar) -> (q, R_bar, 1/rho)
+  Grid g;
+  Coef<T> c;
+  const T* __restrict__ q;
+  const T* __restrict__ rb;
+  T* __restrict__ qbar;
+  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      q0[f] = q[f * N + id];
-      r0[f] = rb[f * N + id];
+      v[G_Q + f] = q[f * g.N + i];
+      v[G_R + f] = rb[f * g.N + i];
     }
-    const T ir0 = recip(q0[0]);
-    T u0[3], vb0[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      u0[a] = q0[a + 1] * ir0;
-      vb0[a] = r0[a + 1] + r0[4] * u0[a];
-    }
-    const T p0 = c.gm1 * (q0[4] - half * (q0[1] * u0[0] + q0[2] * u0[1] + q0[3] * u0[2]));
-    const T T0 = c.gm2 * p0 * ir0;
-
-    T qb[5] = {0, 0, 0, 0, 0};
-    T ub[3] = {0, 0, 0};
-    T pb = 0, Tb = 0;
-    T lap[3] = {0, 0, 0}, X[3] = {0, 0, 0};  // forward viscous pieces at this point
-
-    // The direction loop is not unrolled, so that one direction's sums and
-    // one pair of neighbours are live at a time.
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-      const T u0d = d == 0 ? u0[0] : (d == 1 ? u0[1] : u0[2]);
-      const T s1 = c.c1[d], s2 = c.c2[d];
-      DirSums<T> S;
-      add_pair<1>(S, q, rb, w, N, nb(g, id, ijk, d, -1), nb(g, id, ijk, d, 1), d, viscous, r0, vb0, u0);
-      add_pair<2>(S, q, rb, w, N, nb(g, id, ijk, d, -2), nb(g, id, ijk, d, 2), d, viscous, r0, vb0, u0);
-      T ubd = 0, Xd = 0;  // contributions to ub[d], X[d]
-      const T dud = s1 * S.ud;  // forward D_d u_d at this point
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        const T Dr = s1 * S.r[f];
-        // (1) flux term D_d(q_f u_d): F = 1/2 D_d(R_bar_f)
-        const T F = half * Dr;
-        qb[f] += F * u0d;
-        ubd += F * q0[f];
-        // (2) u_d D_d q_f
-        qb[f] += half * (s1 * S.rud[f]);
-        // (3) q_f D_d u_d, pointwise part
-        qb[f] -= half * r0[f] * dud;
-        // (4) momentum pressure gradient D_d p
-        if (f == d + 1) pb += Dr;
-        if (f == 4) {
-          // (5) pressure work D_d(p u_d)
-          pb += Dr * u0d;
-          ubd += Dr * p0;
-          // (8) heat flux
-          if (viscous) Tb += c.kap * (s2 * S.rE2);
-        }
-      }
-      // (2) -R_bar_f D_d q_f and (3) q_f D_d u_d, stencil part summed over f
-      ubd += half * (s1 * S.ubs);
-      if (viscous) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          // (6) viscous momentum, D2 parts, on V_bar_a = R_bar_{m_a} + R_bar_E u_a
-          const T vb = s2 * S.vb2[a];
-          ub[a] += c.ire * vb;
-          if (a == d) ubd += c.ire * (T(1.0 / 3.0)) * vb;
-          // forward pieces of V_{m_a} at this point
-          const T l = s2 * S.u2[a];
-          lap[a] += l;
-          if (a == d) Xd += l;
-          // (7) viscous work: u_a += D_d^T(G_bar_ad) = -D_d(G_bar_ad)
-          ub[a] -= s1 * S.gb[a];
-        }
-        // (9) mixed second derivatives through the stored inner differences:
-        //   forward X_d += D_d sigma_d ; adjoint u_d += (1/(3 Re)) D_d tau_d
-        Xd += s1 * S.sig;
-        ubd += c.ire * T(1.0 / 3.0) * (s1 * S.tau);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        ub[a] += a == d ? ubd : T(0);
-        X[a] += a == d ? Xd : T(0);
-      }
-    }
-
-    if (viscous) {
-      // pointwise part of sum_a u_a V_{m_a}
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] += r0[4] * (c.ire * (lap[a] + X[a] * T(1.0 / 3.0)));
-    }
-
-    // Chain through the primitive variables at this point.
-    pb += c.gm2 * Tb * ir0;
-    qb[0] -= T0 * Tb * ir0;
-    qb[4] += c.gm1 * pb;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      qb[a + 1] -= half * c.gm1 * pb * u0[a];
-      ub[a] -= half * c.gm1 * pb * q0[a + 1];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      qb[a + 1] += ub[a] * ir0;
-      qb[0] -= ub[a] * u0[a] * ir0;
-    }
-#pragma unroll
-    for (int f = 0; f < 5; ++f) qbar[f * N + id] += qb[f];
   }
-}
+  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
+#pragma unroll
+    for (int f = 0; f < NL; ++f) o[f] = v[f];
+    o[G_IR] = recip(v[G_Q]);
+  }
+  template <int d>
+  __device__ __forceinline__ void direction(const Nbrs<T, NF>& n, bool viscous, Centre<T>& C) const {
+    DirSums<T> S;
+    add_pair<1, d>(S, [&](int f) { return n.template at<d>(f, 1); }, [&](int f) { return n.template at<d>(f, 2); },
+                   viscous, C.r0, C.vb0, C.u0);
+    add_pair<2, d>(S, [&](int f) { return n.template at<d>(f, 0); }, [&](int f) { return n.template at<d>(f, 3); },
+                   viscous, C.r0, C.vb0, C.u0);
+    direction_adjoint<d>(S, viscous, c, C);
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+    const bool viscous = c.viscous != 0;
+    Centre<T> C;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      C.q0[f] = n.c(G_Q + f);
+      C.r0[f] = n.c(G_R + f);
+      C.qb[f] = 0;
+    }
+    C.ir0 = n.c(G_IR);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C.u0[a] = C.q0[a + 1] * C.ir0;
+      C.vb0[a] = C.r0[a + 1] + C.r0[4] * C.u0[a];
+      C.ub[a] = 0;
+      C.lap[a] = 0;
+      C.X[a] = 0;
+    }
+    C.p0 = c.gm1 * (C.q0[4] - T(0.5) * (C.q0[1] * C.u0[0] + C.q0[2] * C.u0[1] + C.q0[3] * C.u0[2]));
+    C.T0 = c.gm2 * C.p0 * C.ir0;
+    C.pb = 0;
+    C.Tb = 0;
+    direction<0>(n, viscous, C);
+    direction<1>(n, viscous, C);
+    direction<2>(n, viscous, C);
+    const T half = T(0.5);
+    if (viscous) {
+      // pointwise part of sum_a u_a V_{m_a}: the Laplacian and the D2_a u_a
+      // part of X_a (its mixed-derivative part is added by pass C)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) C.ub[a] += C.r0[4] * (c.ire * (C.lap[a] + C.X[a] * T(1.0 / 3.0)));
+    }
+    // Chain through the primitive variables at this point.
+    C.pb += c.gm2 * C.Tb * C.ir0;
+    C.qb[0] -= C.T0 * C.Tb * C.ir0;
+    C.qb[4] += c.gm1 * C.pb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C.qb[a + 1] -= half * c.gm1 * C.pb * C.u0[a];
+      C.ub[a] -= half * c.gm1 * C.pb * C.q0[a + 1];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C.qb[a + 1] += C.ub[a] * C.ir0;
+      C.qb[0] -= C.ub[a] * C.u0[a] * C.ir0;
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qbar[f * g.N + id] += C.qb[f];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Pass C (viscous only): the workspace terms.  u_bar_a gets the viscous-work
+// adjoint -sum_d D_d(G_bar_ad) and (1/(3 Re)) D_a tau_a, and the mixed part of
+// the forward X_a = D_a sigma_a enters through R_bar_E (1/Re) X_a / 3; the
+// result is chained through u = m / rho into q_bar.
+// ---------------------------------------------------------------------------
+template <class T>
+struct ViscOp {
+  static constexpr int NL = W_FIELDS, NF = W_FIELDS, kWavesPerEU = 1;
+  Grid g;
+  Coef<T> c;
+  const T* __restrict__ q;
+  const T* __restrict__ rb;
+  const T* __restrict__ w;
+  T* __restrict__ qbar;
+  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
+#pragma unroll
+    for (int f = 0; f < NL; ++f) v[f] = w[f * g.N + i];
+  }
+  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
+#pragma unroll
+    for (int f = 0; f < NL; ++f) o[f] = v[f];
+  }
+  template <int d>
+  __device__ __forceinline__ T D(const Nbrs<T, NF>& n, int f) const {
+    return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
+                      c.c1[d]);
+  }
+  template <int d>
+  __device__ __forceinline__ void direction(const Nbrs<T, NF>& n, T (&ub)[3], T (&X)[3]) const {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] -= D<d>(n, W_GB + sym(a, d));
+    X[d] = D<d>(n, W_SIG + d);
+    // (9) mixed second derivatives through the stored inner differences
+    ub[d] += c.ire * T(1.0 / 3.0) * D<d>(n, W_TAU + d);
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+    const long long N = g.N;
+    T ub[3] = {0, 0, 0}, X[3];
+    direction<0>(n, ub, X);
+    direction<1>(n, ub, X);
+    direction<2>(n, ub, X);
+    const T rE = rb[4 * N + id];
+    const T rho = q[id], ir0 = recip(rho);
+    T qb0 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T uba = ub[a] + rE * (c.ire * (X[a] * T(1.0 / 3.0)));
+      const T ma = q[(a + 1) * N + id];
+      qbar[(a + 1) * N + id] += uba * ir0;
+      qb0 -= uba * (ma * ir0) * ir0;
+    }
+    qbar[id] += qb0;
+  }
+};
 
 // Reversed RK stage: zeta += B q_bar ; r_bar = dt zeta ; zeta = A zeta.
 template <class T>
@@ -487,7 +692,10 @@ inline unsigned blocks_for(long long n) { return blocks_1d(n, kThreads); }
 
 }  // namespace
 
-long long adjoint_work_items(const Grid& g) { return col_march(g).blocks * kThreads; }
+long long adjoint_work_items(const Grid& g) {
+  const long long a = col_march(g).blocks * kThreads, b = plane_march(g).blocks * GNT;
+  return a > b ? a : b;
+}
 
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar, void* qbar,
@@ -495,17 +703,20 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* qq = static_cast<const T*>(q);
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
-  const ColMarch cm = col_march(g);
-  if (c.viscous) {
-    hipLaunchKernelGGL((adj_prim<T>), dim3(blocks_for(g.N)), dim3(kThreads), 0, st, g, qq, rr, w);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((adj_stress<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, rr, w);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((adj_gather<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, qq, rr, w,
-                     static_cast<T*>(qbar));
+  T* qb = static_cast<T*>(qbar);
+  const PlaneMarch pm = plane_march(g);
+  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
+  const dim3 grid((unsigned)pm.blocks), block(GNT);
+  hipLaunchKernelGGL((plane_march_kernel<T, GatherOp<T>>), grid, block, 0, st, g, pm, remap,
+                     GatherOp<T>{g, c, qq, rr, qb});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !c.viscous) return e;
+  hipLaunchKernelGGL((plane_march_kernel<T, StressOp<T>>), grid, block, 0, st, g, pm, remap,
+                     StressOp<T>{g, c, qq, rr, w});
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((plane_march_kernel<T, ViscOp<T>>), grid, block, 0, st, g, pm, remap,
+                     ViscOp<T>{g, c, qq, rr, w, qb});
   return hipGetLastError();
 }
 
