@@ -26,79 +26,8 @@ namespace tgv {
 
 namespace {
 
+// Threads per block of the element-wise reversed RK stage.
 constexpr int kThreads = 256;
-
-__device__ __forceinline__ long long nb(const Grid& g, long long id, const int ijk[3], int d, int s) {
-  if (d == 0) {
-    int t = ijk[0] + s;
-    t += (t < 0) ? g.nx : 0;
-    t -= (t >= g.nx) ? g.nx : 0;
-    return id + (t - ijk[0]);
-  } else if (d == 1) {
-    int t = ijk[1] + s;
-    t += (t < 0) ? g.ny : 0;
-    t -= (t >= g.ny) ? g.ny : 0;
-    return id + (long long)(t - ijk[1]) * g.nx;
-  }
-  int t = ijk[2] + s;
-  t += (t < 0) ? g.nz : 0;
-  t -= (t >= g.nz) ? g.nz : 0;
-  return id + (long long)(t - ijk[2]) * g.plane;
-}
-
-// Gather kernels walk columns: a block owns a CX x CY tile of (x, y) columns
-// and a chunk of kz planes, x fastest, and each thread loops over its column's
-// planes, so the z-neighbour rows it reads were read by the same block a step
-// or two earlier and the tile's x/y neighbours are shared within the block.
-// Blocks are spread over the 8 XCDs in contiguous runs (hardware block b runs
-// on XCD b mod 8).
-constexpr int CX = 64, CY = kThreads / CX;
-
-struct ColMarch {
-  int tiles_x, tiles_y, kz;
-  long long blocks;
-};
-
-ColMarch col_march(const Grid& g) {
-  ColMarch m;
-  m.tiles_x = (g.nx + CX - 1) / CX;
-  m.tiles_y = (g.ny + CY - 1) / CY;
-  // 16 planes per block (measured 3-5 % faster than 64 or 128 at 512^3);
-  // fewer where the grid would otherwise hold too few blocks to fill the chip
-  m.kz = 16;
-  while (m.kz > 1 && (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz) < 2048) m.kz /= 2;
-  m.blocks = (long long)m.tiles_x * m.tiles_y * ((g.nz + m.kz - 1) / m.kz);
-  return m;
-}
-
-struct Column {
-  int x, y, z0, z1;
-  long long xy;
-  bool valid;
-};
-
-__device__ __forceinline__ Column column(const Grid& g, const ColMarch& m) {
-  const int nb = (int)m.blocks;
-  int b = blockIdx.x;
-  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
-  Column c;
-  c.x = (b % m.tiles_x) * CX + threadIdx.x % CX;
-  c.y = ((b / m.tiles_x) % m.tiles_y) * CY + threadIdx.x / CX;
-  c.z0 = (b / (m.tiles_x * m.tiles_y)) * m.kz;
-  c.z1 = min(c.z0 + m.kz, g.nz);
-  c.valid = c.x < g.nx && c.y < g.ny;
-  c.xy = (long long)c.y * g.nx + c.x;
-  return c;
-}
-
-template <class T>
-__device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T s) {
-  return s * (T(8) * (p1 - m1) - (p2 - m2));
-}
-template <class T>
-__device__ __forceinline__ T D2(T m2, T m1, T c0, T p1, T p2, T s) {
-  return s * (T(16) * ((p1 - c0) + (m1 - c0)) - ((p2 - c0) + (m2 - c0)));
-}
 
 // Index of the symmetric pair (a, d) in the 6-component storage.
 __device__ __forceinline__ int sym(int a, int d) {
@@ -626,57 +555,67 @@ __global__ void __launch_bounds__(kThreads) rk_adj(long long n5, T A, T B, T dt,
   }
 }
 
-// eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega.
+// eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega, with the
+// velocity u_a = m_a / rho derived as each plane is staged.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_vort(Grid g, ColMarch cm, Coef<T> c, T scale, const T* __restrict__ q,
-                                                     T* __restrict__ wbar) {
-  const Column col = column(g, cm);
-  if (!col.valid) return;
-#pragma nounroll
-  for (int z = col.z0; z < col.z1; ++z) {
-    const int ijk[3] = {col.x, col.y, z};
-    const long long id = (long long)z * g.plane + col.xy;
-    T G[3][3];
-    const int offs[4] = {-2, -1, 1, 2};
+struct VortOp {
+  static constexpr int NL = 4, NF = 3, kWavesPerEU = 2;  // (rho, m) -> u
+  Grid g;
+  Coef<T> c;
+  T scale;
+  const T* __restrict__ q;
+  T* __restrict__ wbar;
+  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      T u[4][3];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const long long n = nb(g, id, ijk, d, offs[s]);
-        const T ir = recip(q[n]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) u[s][a] = q[(a + 1) * g.N + n] * ir;
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) G[a][d] = D1(u[0][a], u[1][a], u[2][a], u[3][a], c.c1[d]);
-    }
-    wbar[id] = scale * (G[2][1] - G[1][2]);
-    wbar[g.N + id] = scale * (G[0][2] - G[2][0]);
-    wbar[2 * g.N + id] = scale * (G[1][0] - G[0][1]);
+    for (int f = 0; f < NL; ++f) v[f] = q[f * g.N + i];
   }
-}
+  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
+    const T ir = recip(v[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[a] = v[a + 1] * ir;
+  }
+  template <int d>
+  __device__ __forceinline__ T D(const Nbrs<T, NF>& n, int f) const {
+    return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
+                      c.c1[d]);
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+    // G[a][d] = D_d u_a, only the off-diagonal ones enter the vorticity
+    wbar[id] = scale * (D<1>(n, 2) - D<2>(n, 1));
+    wbar[g.N + id] = scale * (D<2>(n, 0) - D<0>(n, 2));
+    wbar[2 * g.N + id] = scale * (D<0>(n, 1) - D<1>(n, 0));
+  }
+};
 
-// eps^S adjoint pass B: u_bar = curl_D(omega_bar), then through u = m / rho.
+// eps^S adjoint pass B: u_bar = curl_D(omega_bar) (D^T = -D turns the
+// transposed curl back into a curl), then through u = m / rho into q_bar.
 template <class T>
-__global__ void __launch_bounds__(kThreads) adj_curl(Grid g, ColMarch cm, Coef<T> c, const T* __restrict__ q,
-                                                     const T* __restrict__ wbar, T* __restrict__ qbar) {
-  const Column col = column(g, cm);
-  if (!col.valid) return;
-#pragma nounroll
-  for (int z = col.z0; z < col.z1; ++z) {
-    const int ijk[3] = {col.x, col.y, z};
-    const long long id = (long long)z * g.plane + col.xy;
+struct CurlOp {
+  static constexpr int NL = 3, NF = 3, kWavesPerEU = 2;
+  Grid g;
+  Coef<T> c;
+  const T* __restrict__ q;
+  const T* __restrict__ wbar;
+  T* __restrict__ qbar;
+  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
+#pragma unroll
+    for (int f = 0; f < NL; ++f) v[f] = wbar[f * g.N + i];
+  }
+  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
+#pragma unroll
+    for (int f = 0; f < NL; ++f) o[f] = v[f];
+  }
+  template <int d>
+  __device__ __forceinline__ T D(const Nbrs<T, NF>& n, int f) const {
+    return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
+                      c.c1[d]);
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
     const long long N = g.N;
-    auto d1w = [&](int comp, int d) {
-      const T* w = wbar + comp * N;
-      return D1(w[nb(g, id, ijk, d, -2)], w[nb(g, id, ijk, d, -1)], w[nb(g, id, ijk, d, 1)],
-                w[nb(g, id, ijk, d, 2)], c.c1[d]);
-    };
     T ub[3];
-    ub[0] = d1w(2, 1) - d1w(1, 2);
-    ub[1] = d1w(0, 2) - d1w(2, 0);
-    ub[2] = d1w(1, 0) - d1w(0, 1);
+    ub[0] = D<1>(n, 2) - D<2>(n, 1);
+    ub[1] = D<2>(n, 0) - D<0>(n, 2);
+    ub[2] = D<0>(n, 1) - D<1>(n, 0);
     const T ir = recip(q[id]);
     T rb = 0;
 #pragma unroll
@@ -686,16 +625,13 @@ __global__ void __launch_bounds__(kThreads) adj_curl(Grid g, ColMarch cm, Coef<T
     }
     qbar[id] += rb;
   }
-}
+};
 
 inline unsigned blocks_for(long long n) { return blocks_1d(n, kThreads); }
 
 }  // namespace
 
-long long adjoint_work_items(const Grid& g) {
-  const long long a = col_march(g).blocks * kThreads, b = plane_march(g).blocks * GNT;
-  return a > b ? a : b;
-}
+long long adjoint_work_items(const Grid& g) { return plane_march(g).blocks * GNT; }
 
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar, void* qbar,
@@ -735,13 +671,17 @@ template <class T>
 hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void* q, double eps_bar, void* qbar,
                                     void* work, hipStream_t st) {
   const T scale = (T)(eps_bar * 2.0 / ((double)g.N) * (double)c.ire);
-  const ColMarch cm = col_march(g);
-  hipLaunchKernelGGL((adj_vort<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, scale,
-                     static_cast<const T*>(q), static_cast<T*>(work));
+  const PlaneMarch pm = plane_march(g);
+  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
+  const dim3 grid((unsigned)pm.blocks), block(GNT);
+  const T* qq = static_cast<const T*>(q);
+  T* w = static_cast<T*>(work);
+  hipLaunchKernelGGL((plane_march_kernel<T, VortOp<T>>), grid, block, 0, st, g, pm, remap,
+                     VortOp<T>{g, c, scale, qq, w});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((adj_curl<T>), dim3((unsigned)cm.blocks), dim3(kThreads), 0, st, g, cm, c, static_cast<const T*>(q),
-                     static_cast<const T*>(work), static_cast<T*>(qbar));
+  hipLaunchKernelGGL((plane_march_kernel<T, CurlOp<T>>), grid, block, 0, st, g, pm, remap,
+                     CurlOp<T>{g, c, qq, w, static_cast<T*>(qbar)});
   return hipGetLastError();
 }
 

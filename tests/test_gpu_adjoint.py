@@ -50,19 +50,21 @@ def test_residual_adjoint_dp_matches_oracle(n, kind, viscous):
     assert np.all(err <= 1e-11 * scale), err / scale
 
 
-# Grids on which the gather kernel runs its benchmark launch: full 16-plane
-# column chunks (the launch shortens them only when a grid has fewer than 2048
-# blocks of 64 x 4 columns), a block count divisible by 8 (XCD-contiguous block
-# order on), ragged x (69 of 2 x 64 columns), y (126 = 31.5 x 4) and z
-# (497 = 31 x 16 + 1: a one-plane last chunk), and 31 chunk seams along z.
+# Grids on which the adjoint passes run a long plane march: the launch gives
+# each block of 32 x 8 columns a chunk of up to 128 planes and halves the chunk
+# (down to 4) until the grid holds at least 1024 blocks.  On 69 x 126 x 497 that
+# is 16-plane chunks and 1536 blocks (a multiple of 8: XCD-contiguous block
+# order on), ragged x (69 of 3 x 32 columns), y (126 of 16 x 8) and z
+# (497 = 31 x 16 + 1: a one-plane last chunk), and 31 chunk seams along z, each
+# with its 3-plane LDS ring restarted.
 FULL_LAUNCH_GRIDS = [(69, 126, 497)]
 
 
-def _col_march(n):
-    """Chunk height and block count of the gather launch on grid n (the rule
-    the kernel's launcher applies)."""
-    tx, ty, kz = -(-n[0] // 64), -(-n[1] // 4), 16
-    while kz > 1 and tx * ty * -(-n[2] // kz) < 2048:
+def _plane_march(n):
+    """Chunk height and block count of the adjoint launch on grid n (the rule
+    the kernels' launcher applies)."""
+    tx, ty, kz = -(-n[0] // 32), -(-n[1] // 8), 128
+    while kz > 4 and tx * ty * -(-n[2] // kz) < 1024:
         kz //= 2
     return kz, tx * ty * -(-n[2] // kz)
 
@@ -70,7 +72,7 @@ def _col_march(n):
 @pytest.mark.parametrize("n", FULL_LAUNCH_GRIDS)
 @pytest.mark.parametrize("viscous", [1, 0])
 def test_residual_adjoint_dp_matches_oracle_in_the_full_launch(n, viscous):
-    kz, blocks = _col_march(n)
+    kz, blocks = _plane_march(n)
     assert kz == 16 and blocks % 8 == 0 and n[2] % kz != 0
     say("adjoint DP full launch", n, viscous, "kz", kz, "blocks", blocks)
     p = tgv.Params(n=n, viscous=viscous)
