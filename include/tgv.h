@@ -38,8 +38,9 @@
  *  - Grid: n_d >= 5 points per axis, spacing h_d = L_d / n_d, x_i = i h_d
  *    (no duplicated periodic end point), N <= 2^34 points (more than any
  *    precision form fits in device memory).  The tiled kernels also need
- *    fewer than 2^32 work-items per dispatch, which only extremely elongated
- *    grids (e.g. 5 x 5 x 2^28) exceed; such grids return NS_ERR_SHAPE.
+ *    fewer than 2^32 work-items per dispatch; their launch rules (long z
+ *    chunks on large grids) keep every grid within the point limit below it,
+ *    and the host check returns NS_ERR_SHAPE should one not be.
  *  - Physics: non-dimensional, constant viscosity mu = 1, Stokes stress,
  *    Fourier heat flux with kappa = 1 / ((gamma-1) M^2 Pr Re),
  *    p = (gamma-1)(rho E - rho |u|^2 / 2), T = gamma M^2 p / rho

@@ -171,24 +171,22 @@ def test_stream_probe_library_loads_and_validates_on_the_host():
 
 def test_grid_size_limits_are_validated_before_launch():
     """N <= 2^34 is accepted by the parameter check (the element-wise kernels
-    loop grid-stride, so no 1-D dispatch limit applies); a tiled launch that
-    would need 2^32 or more work-items in one dispatch is refused with
-    NS_ERR_SHAPE before any HIP call (the pointers here are never touched)."""
+    loop grid-stride, so no 1-D dispatch limit applies); larger grids are
+    refused with NS_ERR_SHAPE before any HIP call (the pointers here are never
+    touched).  The tiled launches (at most 2^34 / (256 x 128) blocks of 256 or
+    512 threads for the plane marches) stay below the 2^32 work-items of one
+    dispatch for every grid that passes this check."""
     lib = tgv.load()
     prec = tgv.PRESETS["DP"]
     big = tgv.Params(n=(4096, 4096, 1025))  # 2^34 + 2^24 points
     assert _call_residual(big, prec) == NS_ERR_SHAPE
     assert "2^34" in tgv.ns_last_error()
-    # 5 x 5 x 2^28: within 2^34 points, but the adjoint's column march would
-    # need 2^24 blocks of 256 threads
-    thin = tgv.Params(n=(5, 5, 1 << 28))
-    rc = lib.ns_residual_adjoint(ctypes.byref(thin.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
-                                 ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None)
-    assert rc == NS_ERR_SHAPE
-    assert "work-items" in tgv.ns_last_error()
-    rc = lib.flow_integrals_adjoint(ctypes.byref(thin.c()), ctypes.byref(prec.c()), ctypes.c_void_p(0x1000),
-                                    ctypes.c_double(1.0), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None)
-    assert rc == NS_ERR_SHAPE
+    for fn, args in (("ns_residual_adjoint", [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(4)]),
+                     ("flow_integrals_adjoint", [ctypes.c_void_p(0x1000), ctypes.c_double(1.0),
+                                                 ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)])):
+        rc = getattr(lib, fn)(ctypes.byref(big.c()), ctypes.byref(prec.c()), *args, None)
+        assert rc == NS_ERR_SHAPE, fn
+        assert "2^34" in tgv.ns_last_error()
 
 
 def test_noalloc_integrals_refuse_grids_beyond_the_static_scratch():
