@@ -828,9 +828,15 @@ template <>
 struct NxtOf<f16, h2> {  // the stored pair is already the lane value
   using type = h2;
 };
+template <>
+struct NxtOf<f16, float> {  // FP16 storage, FP32 arithmetic: converted when written to LDS
+  using type = f16;
+};
 template <class Tc, class Tq, int N>
 __device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_load(const Tq (&e)[N], int i) {
-  if constexpr (kLanes<Tc> == 1)
+  if constexpr (kLanes<Tc> == 1 && std::is_same<typename NxtOf<Tq, Tc>::type, Tq>::value)
+    return e[i];
+  else if constexpr (kLanes<Tc> == 1)
     return load_as<Tc>(e[i]);
   else if constexpr (std::is_same<Tq, f16>::value)
     return h2{e[2 * i], e[2 * i + 1]};
@@ -839,7 +845,9 @@ __device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_load(const Tq (&e)[N
 }
 template <class Tc, class N>
 __device__ __forceinline__ Tc nxt_value(const N& v) {
-  if constexpr (kLanes<Tc> == 1 || std::is_same<N, h2>::value)
+  if constexpr (kLanes<Tc> == 1 && !std::is_same<N, Tc>::value)
+    return load_as<Tc>(v);
+  else if constexpr (kLanes<Tc> == 1 || std::is_same<N, h2>::value)
     return v;
   else
     return lane_load<Tc>(v.e);
@@ -847,7 +855,7 @@ __device__ __forceinline__ Tc nxt_value(const N& v) {
 template <class Tc, class Tq>
 __device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_pad() {
   if constexpr (kLanes<Tc> == 1)
-    return Tc(1);
+    return typename NxtOf<Tq, Tc>::type(1);
   else if constexpr (std::is_same<Tq, f16>::value)
     return h2{f16(1), f16(1)};
   else
@@ -1248,7 +1256,7 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
     // run 2-12 % slower with them (a few spilled registers) and keep V = 1.
     // The single-role kernel below takes pairs in every form it runs (SPDP
     // fused 2 %, SP_DPC 3.5 % faster).
-    constexpr bool kPairs = sizeof(Tc) == 8;
+    constexpr bool kPairs = sizeof(Tc) == 8 || std::is_same<Tq, f16>::value;
     if (kPairs && g.nx % 2 == 0)
       hipLaunchKernelGGL((residual_ws<Tq, Tr, Tc, Tqt, Ta, FUSED, SPLIT, kWtx, kWty, kPairs ? 2 : 1>),
                          dim3((unsigned)nb), dim3(Ws<kWtx, kWty>::NT), 0, st, K, rk, tiles_x, tiles_y, kz, remap);
