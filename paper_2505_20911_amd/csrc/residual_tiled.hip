@@ -832,6 +832,10 @@ template <>
 struct NxtOf<f16, float> {  // FP16 storage, FP32 arithmetic: converted when written to LDS
   using type = f16;
 };
+template <>
+struct NxtOf<float, double> {  // FP32 storage, FP64 arithmetic: likewise (and half the registers)
+  using type = float;
+};
 template <class Tc, class Tq, int N>
 __device__ __forceinline__ typename NxtOf<Tq, Tc>::type nxt_load(const Tq (&e)[N], int i) {
   if constexpr (kLanes<Tc> == 1 && std::is_same<typename NxtOf<Tq, Tc>::type, Tq>::value)
@@ -1225,9 +1229,10 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
   // kernel, on 32 x 8 tiles for FP64 arithmetic (256 columns per role, as
   // many as the registers allow; a 36 x 12 plane has fewer halo points to
   // load and convert than 68 x 8) and 64 x 8 tiles for FP32 arithmetic; the
-  // single-role kernel for two forms where it is faster: the fused stage
-  // with FP64 Q and FP32 arithmetic (its Q_in ring does not fit the z role's
-  // registers) and FP32 Q with FP64 arithmetic.
+  // single-role kernel for the fused stage with FP64 Q and FP32 arithmetic,
+  // where it is faster (its Q_in ring does not fit the z role's registers).
+  // FP32 Q with FP64 arithmetic runs the warp-specialised kernel on FP64
+  // geometry, its prefetched plane held in FP32 until written to LDS.
   if constexpr (std::is_same<Tc, f16>::value) {
     // FP16 arithmetic: packed pairs of x-points in the warp-specialised
     // kernel when nx is even (pairs never cross the periodic wrap and are
@@ -1242,7 +1247,7 @@ hipError_t launch_tiled(const Grid& g, const Coef<Tc>& c, const void* q, void* r
     }
   }
   constexpr bool kQinExact = sizeof(Tc) >= sizeof(Tq) && std::is_same<Ta, Tc>::value;
-  constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8) && !(sizeof(Tc) == 8 && sizeof(Tq) < 8);
+  constexpr bool kWs = !(FUSED && !kQinExact && sizeof(Tc) < 8);
   constexpr int kWtx = sizeof(Tc) == 8 ? 32 : 64, kWty = 8;
   constexpr int kTx = kWs ? kWtx : TX, kTy = kWs ? kWty : TY;
   const TileLaunch L = tile_launch(g, kTx, kTy);
