@@ -431,7 +431,7 @@ template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPL
 __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<Tq, Tqt, Ta>& rk, Ctx<Tc>& cx,
                                       QRing<Tq>& qr,
                                       Tc* lds, Tc* lds_ri, int ri_slot_p, int ri_slot_k,
-                                      Tc (&nxt)[Sr<V>::LOADS][V][5], const long long (&off)[Sr<V>::LOADS], int p,
+                                      Tq (&nxt)[Sr<V>::LOADS][V][5], const long long (&off)[Sr<V>::LOADS], int p,
                                       int kout_lo, int kout_hi, bool col_valid, long long col_off, int p_last) {
   constexpr int VPR = Sr<V>::VPR, NVS = Sr<V>::NVS, VLOADS = Sr<V>::LOADS;
   // the window holds Q converted exactly to Tc when Tc is at least as wide as Tq
@@ -456,8 +456,10 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
       const int s0 = (sv / VPR) * HX + (sv % VPR) * V;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        Tc f[NF];
-        primitives(nxt[l][e], f, c);
+        Tc qv[5], f[NF];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) qv[m] = load_as<Tc>(nxt[l][e][m]);
+        primitives(qv, f, c);
 #pragma unroll
         for (int k = 0; k < NF; ++k) lds[k * NPL + s0 + e] = f[k];
       }
@@ -483,7 +485,7 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
         for (int f = 0; f < 5; ++f) {
           const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
 #pragma unroll
-          for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = v.e[e];
         }
       }
     }
@@ -647,8 +649,10 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   const bool col_valid = cxg < g.nx && cyg < g.ny;
   const long long col_off = (long long)cyg * g.nx + cxg;
 
-  // prefetch the first plane
-  Tc nxt[VLOADS][V][5];
+  // prefetch the first plane (kept in the storage type until it is
+  // converted for LDS a step later: a conversion right after the load would
+  // make the wave wait for its data there)
+  Tq nxt[VLOADS][V][5];
   {
     int z = z0 - 2;
     z += (z < 0) ? g.nz : 0;
@@ -662,10 +666,10 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
         if (sv < NVS) {
           const Run<Tq, V> v = *reinterpret_cast<const Run<Tq, V>*>(K.q + f * g.N + zo + off[l]);
 #pragma unroll
-          for (int e = 0; e < V; ++e) nxt[l][e][f] = load_as<Tc>(v.e[e]);
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = v.e[e];
         } else {
 #pragma unroll
-          for (int e = 0; e < V; ++e) nxt[l][e][f] = Tc(1);
+          for (int e = 0; e < V; ++e) nxt[l][e][f] = Tq(1);
         }
       }
     }
