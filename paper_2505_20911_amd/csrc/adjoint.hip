@@ -54,8 +54,11 @@ static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 // block (plus the halo), where gathering each stencil neighbour from global
 // memory re-read it many times through the caches.  The next plane is
 // requested before the current plane's arithmetic.  An operator supplies NL
-// values loaded per point (load), the NF fields staged from them (derive), and
-// the output of one point (emit).
+// values loaded per point (load), the NF fields staged from them (derive), the
+// values of the output point it reads from global memory (early: requested
+// before the next plane, so their latency overlaps the arithmetic rather than
+// being waited for at the end of the step), and the output of one point
+// (emit).
 // ---------------------------------------------------------------------------
 constexpr int GTX = 32, GTY = 8, GNT = GTX * GTY;
 constexpr int GHX = GTX + 4, GHY = GTY + 4, GNP = GHX * GHY;
@@ -180,11 +183,14 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   for (int cz = z0; cz < z1; ++cz) {
     stash(cz + 2);
     __syncthreads();
+    const long long id = zoff(cz) + col_off;
+    typename Op::Early early;
+    if (valid) op.early(id, early);
     if (cz + 3 <= z1 + 1) fetch(cz + 3);
     const T* Pc = lds[(cz - z0 + 3) % GSLOTS];
     if (valid) {
       const Nbrs<T, NF> nbr{Pc, lds[(cz + 1 - z0 + 3) % GSLOTS], lds[(cz + 2 - z0 + 3) % GSLOTS], wm1, wm2, own};
-      op.emit(nbr, zoff(cz) + col_off);
+      op.emit(nbr, id, early);
     }
     // the own column of plane c moves to the registers before its slot is
     // overwritten by plane c + 3
@@ -197,6 +203,12 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   }
 }
 
+// Operators that read nothing at the output point.
+struct NoEarly {
+  struct Early {};
+  __device__ __forceinline__ void early(long long, Early&) const {}
+};
+
 template <class T>
 __device__ __forceinline__ T first_diff(T m2, T m1, T p1, T p2, T s) {
   return s * (T(8) * (p1 - m1) - (p2 - m2));
@@ -208,7 +220,7 @@ __device__ __forceinline__ T first_diff(T m2, T m1, T p1, T p2, T s) {
 // once per point as it is staged.
 // ---------------------------------------------------------------------------
 template <class T>
-struct StressOp {
+struct StressOp : NoEarly {
   static constexpr int NL = 8, NF = 7, kWavesPerEU = 2;  // (rho, m, R_bar_m, R_bar_E) -> (u, V_bar, R_bar_E)
   Grid g;
   Coef<T> c;
@@ -236,7 +248,7 @@ struct StressOp {
     return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
                       c.c1[d]);
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early&) const {
     const long long N = g.N;
     T G[3][3];
 #pragma unroll
@@ -436,7 +448,14 @@ struct GatherOp {
                    viscous, C.r0, C.vb0, C.u0);
     direction_adjoint<d>(S, viscous, c, C);
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+  struct Early {
+    T qb[5];
+  };
+  __device__ __forceinline__ void early(long long id, Early& e) const {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) e.qb[f] = qbar[f * g.N + id];
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early& e) const {
     const bool viscous = c.viscous != 0;
     Centre<T> C;
 #pragma unroll
@@ -483,7 +502,7 @@ struct GatherOp {
       C.qb[0] -= C.ub[a] * C.u0[a] * C.ir0;
     }
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qbar[f * g.N + id] += C.qb[f];
+    for (int f = 0; f < 5; ++f) qbar[f * g.N + id] = e.qb[f] + C.qb[f];
   }
 };
 
@@ -523,23 +542,33 @@ struct ViscOp {
     // (9) mixed second derivatives through the stored inner differences
     ub[d] += c.ire * T(1.0 / 3.0) * D<d>(n, W_TAU + d);
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+  struct Early {
+    T rE, rho, m[3], qb[4];
+  };
+  __device__ __forceinline__ void early(long long id, Early& e) const {
+    const long long N = g.N;
+    e.rE = rb[4 * N + id];
+    e.rho = q[id];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e.m[a] = q[(a + 1) * N + id];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) e.qb[f] = qbar[f * N + id];
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early& e) const {
     const long long N = g.N;
     T ub[3] = {0, 0, 0}, X[3];
     direction<0>(n, ub, X);
     direction<1>(n, ub, X);
     direction<2>(n, ub, X);
-    const T rE = rb[4 * N + id];
-    const T rho = q[id], ir0 = recip(rho);
+    const T ir0 = recip(e.rho);
     T qb0 = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T uba = ub[a] + rE * (c.ire * (X[a] * T(1.0 / 3.0)));
-      const T ma = q[(a + 1) * N + id];
-      qbar[(a + 1) * N + id] += uba * ir0;
-      qb0 -= uba * (ma * ir0) * ir0;
+      const T uba = ub[a] + e.rE * (c.ire * (X[a] * T(1.0 / 3.0)));
+      qbar[(a + 1) * N + id] = e.qb[a + 1] + uba * ir0;
+      qb0 -= uba * (e.m[a] * ir0) * ir0;
     }
-    qbar[id] += qb0;
+    qbar[id] = e.qb[0] + qb0;
   }
 };
 
@@ -558,7 +587,7 @@ __global__ void __launch_bounds__(kThreads) rk_adj(long long n5, T A, T B, T dt,
 // eps^S adjoint pass A: omega_bar = eps_bar (1/(N Re)) 2 omega, with the
 // velocity u_a = m_a / rho derived as each plane is staged.
 template <class T>
-struct VortOp {
+struct VortOp : NoEarly {
   static constexpr int NL = 4, NF = 3, kWavesPerEU = 2;  // (rho, m) -> u
   Grid g;
   Coef<T> c;
@@ -579,7 +608,7 @@ struct VortOp {
     return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
                       c.c1[d]);
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early&) const {
     // G[a][d] = D_d u_a, only the off-diagonal ones enter the vorticity
     wbar[id] = scale * (D<1>(n, 2) - D<2>(n, 1));
     wbar[g.N + id] = scale * (D<2>(n, 0) - D<0>(n, 2));
@@ -610,20 +639,30 @@ struct CurlOp {
     return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
                       c.c1[d]);
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id) const {
+  struct Early {
+    T q[4], qb[4];
+  };
+  __device__ __forceinline__ void early(long long id, Early& e) const {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      e.q[f] = q[f * g.N + id];
+      e.qb[f] = qbar[f * g.N + id];
+    }
+  }
+  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early& e) const {
     const long long N = g.N;
     T ub[3];
     ub[0] = D<1>(n, 2) - D<2>(n, 1);
     ub[1] = D<2>(n, 0) - D<0>(n, 2);
     ub[2] = D<0>(n, 1) - D<1>(n, 0);
-    const T ir = recip(q[id]);
+    const T ir = recip(e.q[0]);
     T rb = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      qbar[(a + 1) * N + id] += ub[a] * ir;
-      rb -= ub[a] * q[(a + 1) * N + id] * ir * ir;
+      qbar[(a + 1) * N + id] = e.qb[a + 1] + ub[a] * ir;
+      rb -= ub[a] * e.q[a + 1] * ir * ir;
     }
-    qbar[id] += rb;
+    qbar[id] = e.qb[0] + rb;
   }
 };
 
@@ -648,7 +687,7 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !c.viscous) return e;
   hipLaunchKernelGGL((plane_march_kernel<T, StressOp<T>>), grid, block, 0, st, g, pm, remap,
-                     StressOp<T>{g, c, qq, rr, w});
+                     StressOp<T>{{}, g, c, qq, rr, w});
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((plane_march_kernel<T, ViscOp<T>>), grid, block, 0, st, g, pm, remap,
@@ -677,7 +716,7 @@ hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void*
   const T* qq = static_cast<const T*>(q);
   T* w = static_cast<T*>(work);
   hipLaunchKernelGGL((plane_march_kernel<T, VortOp<T>>), grid, block, 0, st, g, pm, remap,
-                     VortOp<T>{g, c, scale, qq, w});
+                     VortOp<T>{{}, g, c, scale, qq, w});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((plane_march_kernel<T, CurlOp<T>>), grid, block, 0, st, g, pm, remap,
