@@ -258,12 +258,12 @@ struct StressOp : NoEarly {
       G[a][2] = D<2>(n, a);
     }
     const T dv[3] = {D<0>(n, 3), D<1>(n, 4), D<2>(n, 5)};  // D_a V_bar_a
-    w[(W_SIG + 0) * N + id] = G[1][1] + G[2][2];
-    w[(W_SIG + 1) * N + id] = G[0][0] + G[2][2];
-    w[(W_SIG + 2) * N + id] = G[0][0] + G[1][1];
-    w[(W_TAU + 0) * N + id] = dv[1] + dv[2];
-    w[(W_TAU + 1) * N + id] = dv[0] + dv[2];
-    w[(W_TAU + 2) * N + id] = dv[0] + dv[1];
+    stream_store(&w[(W_SIG + 0) * N + id], G[1][1] + G[2][2]);
+    stream_store(&w[(W_SIG + 1) * N + id], G[0][0] + G[2][2]);
+    stream_store(&w[(W_SIG + 2) * N + id], G[0][0] + G[1][1]);
+    stream_store(&w[(W_TAU + 0) * N + id], dv[1] + dv[2]);
+    stream_store(&w[(W_TAU + 1) * N + id], dv[0] + dv[2]);
+    stream_store(&w[(W_TAU + 2) * N + id], dv[0] + dv[1]);
     const T div = G[0][0] + G[1][1] + G[2][2];
     const T two_rE = T(2) * n.c(6);
 #pragma unroll
@@ -271,7 +271,7 @@ struct StressOp : NoEarly {
 #pragma unroll
       for (int d = a; d < 3; ++d) {
         const T tau = c.ire * (G[a][d] + G[d][a] - (a == d ? T(2.0 / 3.0) * div : T(0)));
-        w[(W_GB + sym(a, d)) * N + id] = two_rE * tau;
+        stream_store(&w[(W_GB + sym(a, d)) * N + id], two_rE * tau);
       }
   }
 };
@@ -502,7 +502,7 @@ struct GatherOp {
       C.qb[0] -= C.ub[a] * C.u0[a] * C.ir0;
     }
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qbar[f * g.N + id] = e.qb[f] + C.qb[f];
+    for (int f = 0; f < 5; ++f) stream_store(&qbar[f * g.N + id], e.qb[f] + C.qb[f]);
   }
 };
 
@@ -565,10 +565,10 @@ struct ViscOp {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const T uba = ub[a] + e.rE * (c.ire * (X[a] * T(1.0 / 3.0)));
-      qbar[(a + 1) * N + id] = e.qb[a + 1] + uba * ir0;
+      stream_store(&qbar[(a + 1) * N + id], e.qb[a + 1] + uba * ir0);
       qb0 -= uba * (e.m[a] * ir0) * ir0;
     }
-    qbar[id] = e.qb[0] + qb0;
+    stream_store(&qbar[id], e.qb[0] + qb0);
   }
 };
 
