@@ -53,7 +53,7 @@ def test_trajectory_256_matches_oracle():
     assert np.all(np.abs(hist[:, 4:7] - h_ref[:, 4:7]) <= 1e-13 * np.abs(h_ref[:, 3:4]))
     # scale of each field's rounding: its own magnitude, except that the three
     # momentum components share the magnitude of the momentum vector (w-momentum
-    # starts at zero and is ~200x smaller than the others after 40 steps, but is
+    # starts at zero and stays far smaller than the others over the run, but is
     # computed from the O(1) components and rounds at their level)
     scale = np.abs(q_ref).max(0)
     scale[1:4] = scale[1:4].max()
