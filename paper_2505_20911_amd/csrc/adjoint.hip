@@ -106,10 +106,27 @@ struct Nbrs {
   }
 };
 
+// The NL values of one point, field f read from op.src(f) at offset i.
 template <class T, class Op>
+__device__ __forceinline__ void load_point(const Op& op, long long i, T (&v)[Op::NL]) {
+#pragma unroll
+  for (int f = 0; f < Op::NL; ++f) v[f] = op.src(f)[i];
+}
+
+// PAIRS (nx even): the halo plane is loaded in aligned runs of two x-points,
+// one 2-element vector load per field for 216 of the 256 threads, instead
+// of two single loads (432 points); tile origins and the halo width are even,
+// so a run never crosses the periodic wrap and the 16-byte alignment of the
+// arrays carries over to every run.
+template <class T, class Op, bool PAIRS>
 __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid g, PlaneMarch pm, int remap, Op op) {
   constexpr int NF = Op::NF, NL = Op::NL;
-  __shared__ T lds[GSLOTS][NF * GNP];
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  constexpr int NSLOT = PAIRS ? 1 : GLOADS;  // load slots per thread
+  constexpr int NRUN = PAIRS ? GNP / 2 : GNP;  // runs per plane
+  constexpr int RX = PAIRS ? GHX / 2 : GHX;    // runs per halo row
+  static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
+  __shared__ __align__(16) T lds[GSLOTS][NF * GNP];
   const int nblk = gridDim.x;
   int b = blockIdx.x;
   if (remap) b = (b % 8) * (nblk / 8) + b / 8;
@@ -124,40 +141,61 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   const long long col_off = (long long)cy * g.nx + cx;
   const int own = (ly + 2) * GHX + (lx + 2);
 
-  // the halo-plane points this thread stages
-  long long off[GLOADS];
+  // the halo-plane runs this thread stages: grid offset and LDS index of the
+  // run's first point
+  long long off[NSLOT];
+  int sl[NSLOT];
 #pragma unroll
-  for (int l = 0; l < GLOADS; ++l) {
+  for (int l = 0; l < NSLOT; ++l) {
     const int s = tid + l * GNT;
-    const int hx = s % GHX, hy = s / GHX;
+    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
     int x = (x0 - 2 + hx) % g.nx;
     x += (x < 0) ? g.nx : 0;
     int y = (y0 - 2 + hy) % g.ny;
     y += (y < 0) ? g.ny : 0;
     off[l] = (long long)y * g.nx + x;
+    sl[l] = hy * GHX + hx;
   }
   auto zoff = [&](int z) {
     z += (z < 0) ? g.nz : 0;
     z -= (z >= g.nz) ? g.nz : 0;
     return (long long)z * g.plane;
   };
-  T pre[GLOADS][NL];
+  T pre[NSLOT][PAIRS ? 2 : 1][NL];
   auto fetch = [&](int z) {
     const long long zo = zoff(z);
 #pragma unroll
-    for (int l = 0; l < GLOADS; ++l)
-      if (tid + l * GNT < GNP) op.load(zo + off[l], pre[l]);
+    for (int l = 0; l < NSLOT; ++l)
+      if (tid + l * GNT < NRUN) {
+        if constexpr (PAIRS) {
+#pragma unroll
+          for (int f = 0; f < NL; ++f) {
+            const T2 v = *reinterpret_cast<const T2*>(op.src(f) + zo + off[l]);
+            pre[l][0][f] = v.x;
+            pre[l][PAIRS ? 1 : 0][f] = v.y;
+          }
+        } else {
+          load_point<T>(op, zo + off[l], pre[l][0]);
+        }
+      }
   };
   auto stash = [&](int z) {
     T* P = lds[(z - z0 + 3) % GSLOTS];
 #pragma unroll
-    for (int l = 0; l < GLOADS; ++l) {
-      const int s = tid + l * GNT;
-      if (s < GNP) {
-        T v[NF];
-        op.derive(pre[l], v);
+    for (int l = 0; l < NSLOT; ++l) {
+      if (tid + l * GNT < NRUN) {
+        if constexpr (PAIRS) {
+          T v0[NF], v1[NF];
+          op.derive(pre[l][0], v0);
+          op.derive(pre[l][PAIRS ? 1 : 0], v1);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) P[f * GNP + s] = v[f];
+          for (int f = 0; f < NF; ++f) *reinterpret_cast<T2*>(&P[f * GNP + sl[l]]) = T2{v0[f], v1[f]};
+        } else {
+          T v[NF];
+          op.derive(pre[l][0], v);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) P[f * GNP + sl[l]] = v[f];
+        }
       }
     }
   };
@@ -167,9 +205,9 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   for (int f = 0; f < NF; ++f) wm2[f] = wm1[f] = T(0);
   if (valid) {
     T raw[NL];
-    op.load(zoff(z0 - 2) + col_off, raw);
+    load_point<T>(op, zoff(z0 - 2) + col_off, raw);
     op.derive(raw, wm2);
-    op.load(zoff(z0 - 1) + col_off, raw);
+    load_point<T>(op, zoff(z0 - 1) + col_off, raw);
     op.derive(raw, wm1);
   }
   // planes z0 and z0 + 1 into LDS, z0 + 2 requested
@@ -203,6 +241,18 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   }
 }
 
+template <class T, class Op>
+hipError_t launch_march(const Grid& g, const Op& op, hipStream_t st) {
+  const PlaneMarch pm = plane_march(g);
+  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
+  const dim3 grid((unsigned)pm.blocks), block(GNT);
+  if (g.nx % 2 == 0)
+    hipLaunchKernelGGL((plane_march_kernel<T, Op, true>), grid, block, 0, st, g, pm, remap, op);
+  else
+    hipLaunchKernelGGL((plane_march_kernel<T, Op, false>), grid, block, 0, st, g, pm, remap, op);
+  return hipGetLastError();
+}
+
 // Operators that read nothing at the output point.
 struct NoEarly {
   struct Early {};
@@ -227,12 +277,7 @@ struct StressOp : NoEarly {
   const T* __restrict__ q;
   const T* __restrict__ rb;
   T* __restrict__ w;
-  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
-#pragma unroll
-    for (int f = 0; f < 4; ++f) v[f] = q[f * g.N + i];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) v[4 + f] = rb[(f + 1) * g.N + i];
-  }
+  __device__ __forceinline__ const T* src(int f) const { return f < 4 ? q + f * g.N : rb + (f - 3) * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
     const T ir = recip(v[0]);
 #pragma unroll
@@ -427,13 +472,7 @@ struct GatherOp {
   const T* __restrict__ q;
   const T* __restrict__ rb;
   T* __restrict__ qbar;
-  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      v[G_Q + f] = q[f * g.N + i];
-      v[G_R + f] = rb[f * g.N + i];
-    }
-  }
+  __device__ __forceinline__ const T* src(int f) const { return f < G_R ? q + f * g.N : rb + (f - G_R) * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
 #pragma unroll
     for (int f = 0; f < NL; ++f) o[f] = v[f];
@@ -521,10 +560,7 @@ struct ViscOp {
   const T* __restrict__ rb;
   const T* __restrict__ w;
   T* __restrict__ qbar;
-  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
-#pragma unroll
-    for (int f = 0; f < NL; ++f) v[f] = w[f * g.N + i];
-  }
+  __device__ __forceinline__ const T* src(int f) const { return w + f * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
 #pragma unroll
     for (int f = 0; f < NL; ++f) o[f] = v[f];
@@ -594,10 +630,7 @@ struct VortOp : NoEarly {
   T scale;
   const T* __restrict__ q;
   T* __restrict__ wbar;
-  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
-#pragma unroll
-    for (int f = 0; f < NL; ++f) v[f] = q[f * g.N + i];
-  }
+  __device__ __forceinline__ const T* src(int f) const { return q + f * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
     const T ir = recip(v[0]);
 #pragma unroll
@@ -626,10 +659,7 @@ struct CurlOp {
   const T* __restrict__ q;
   const T* __restrict__ wbar;
   T* __restrict__ qbar;
-  __device__ __forceinline__ void load(long long i, T (&v)[NL]) const {
-#pragma unroll
-    for (int f = 0; f < NL; ++f) v[f] = wbar[f * g.N + i];
-  }
+  __device__ __forceinline__ const T* src(int f) const { return wbar + f * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
 #pragma unroll
     for (int f = 0; f < NL; ++f) o[f] = v[f];
@@ -679,20 +709,11 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
   T* qb = static_cast<T*>(qbar);
-  const PlaneMarch pm = plane_march(g);
-  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
-  const dim3 grid((unsigned)pm.blocks), block(GNT);
-  hipLaunchKernelGGL((plane_march_kernel<T, GatherOp<T>>), grid, block, 0, st, g, pm, remap,
-                     GatherOp<T>{g, c, qq, rr, qb});
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_march<T>(g, GatherOp<T>{g, c, qq, rr, qb}, st);
   if (e != hipSuccess || !c.viscous) return e;
-  hipLaunchKernelGGL((plane_march_kernel<T, StressOp<T>>), grid, block, 0, st, g, pm, remap,
-                     StressOp<T>{{}, g, c, qq, rr, w});
-  e = hipGetLastError();
+  e = launch_march<T>(g, StressOp<T>{{}, g, c, qq, rr, w}, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((plane_march_kernel<T, ViscOp<T>>), grid, block, 0, st, g, pm, remap,
-                     ViscOp<T>{g, c, qq, rr, w, qb});
-  return hipGetLastError();
+  return launch_march<T>(g, ViscOp<T>{g, c, qq, rr, w, qb}, st);
 }
 
 template <class T>
@@ -710,18 +731,11 @@ template <class T>
 hipError_t launch_integrals_adjoint(const Grid& g, const Coef<T>& c, const void* q, double eps_bar, void* qbar,
                                     void* work, hipStream_t st) {
   const T scale = (T)(eps_bar * 2.0 / ((double)g.N) * (double)c.ire);
-  const PlaneMarch pm = plane_march(g);
-  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
-  const dim3 grid((unsigned)pm.blocks), block(GNT);
   const T* qq = static_cast<const T*>(q);
   T* w = static_cast<T*>(work);
-  hipLaunchKernelGGL((plane_march_kernel<T, VortOp<T>>), grid, block, 0, st, g, pm, remap,
-                     VortOp<T>{{}, g, c, scale, qq, w});
-  hipError_t e = hipGetLastError();
+  const hipError_t e = launch_march<T>(g, VortOp<T>{{}, g, c, scale, qq, w}, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((plane_march_kernel<T, CurlOp<T>>), grid, block, 0, st, g, pm, remap,
-                     CurlOp<T>{g, c, qq, w, static_cast<T*>(qbar)});
-  return hipGetLastError();
+  return launch_march<T>(g, CurlOp<T>{g, c, qq, w, static_cast<T*>(qbar)}, st);
 }
 
 template hipError_t launch_residual_adjoint<double>(const Grid&, const Coef<double>&, const void*, const void*, void*,

@@ -56,8 +56,10 @@ def test_residual_adjoint_dp_matches_oracle(n, kind, viscous):
 # is 16-plane chunks and 1536 blocks (a multiple of 8: XCD-contiguous block
 # order on), ragged x (69 of 3 x 32 columns), y (126 of 16 x 8) and z
 # (497 = 31 x 16 + 1: a one-plane last chunk), and 31 chunk seams along z, each
-# with its 3-plane LDS ring restarted.
-FULL_LAUNCH_GRIDS = [(69, 126, 497)]
+# with its 3-plane LDS ring restarted.  With odd nx the halo plane is loaded one
+# point per lane; 70 x 126 x 497 is the same launch with even nx, where it is
+# loaded in aligned x-pairs (the pairs crossing x = 0 of the periodic halo too).
+FULL_LAUNCH_GRIDS = [(69, 126, 497), (70, 126, 497)]
 
 
 def _plane_march(n):
