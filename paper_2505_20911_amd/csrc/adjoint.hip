@@ -253,6 +253,160 @@ hipError_t launch_march(const Grid& g, const Op& op, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Plane march for operators that difference only a few of their fields along
+// z and take no pointwise derivation while staging (the loaded values are the
+// staged ones).  LDS holds only the NP fields differenced along x or y, on the
+// tile plus halo, double-buffered (planes c and c + 1, one barrier per plane);
+// the NZ fields differenced along z come from a register window over the own
+// column (planes c - 2 .. c + 2), each loaded by its own thread three planes
+// ahead.  Against the three-plane ring this halves the LDS per block for the
+// same number of loads per point.
+// ---------------------------------------------------------------------------
+template <class T, int NP, int NZ>
+struct NbrsZ {
+  const T* Pc;
+  const T (*zw)[NZ];
+  int own;
+  // plane field f at the output point
+  __device__ __forceinline__ T c(int f) const { return Pc[f * GNP + own]; }
+  // plane field f at offset index s (0..3 = -2, -1, +1, +2) along x (d = 0) or y
+  template <int d>
+  __device__ __forceinline__ T at(int f, int s) const {
+    static_assert(d < 2, "plane fields are differenced along x and y");
+    constexpr int st = d == 0 ? 1 : GHX;
+    const int o = (s < 2) ? (s - 2) : (s - 1);
+    return Pc[f * GNP + own + o * st];
+  }
+  // z-field k at offset index s along z
+  __device__ __forceinline__ T atz(int k, int s) const { return zw[s < 2 ? s : s + 1][k]; }
+};
+
+template <class T, class Op, bool PAIRS>
+__global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_z_kernel(Grid g, PlaneMarch pm, int remap,
+                                                                             Op op) {
+  constexpr int NP = Op::NP, NZ = Op::NZ;
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  constexpr int NSLOT = PAIRS ? 1 : GLOADS;
+  constexpr int NRUN = PAIRS ? GNP / 2 : GNP;
+  constexpr int RX = PAIRS ? GHX / 2 : GHX;
+  static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
+  __shared__ __align__(16) T lds[2][NP * GNP];
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
+  const int x0 = (b % pm.tiles_x) * GTX;
+  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
+  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  const int z1 = min(z0 + pm.kz, g.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % GTX, ly = tid / GTX;
+  const int cx = x0 + lx, cy = y0 + ly;
+  const bool valid = cx < g.nx && cy < g.ny;
+  const long long col_off = (long long)cy * g.nx + cx;
+  const int own = (ly + 2) * GHX + (lx + 2);
+
+  long long off[NSLOT];
+  int sl[NSLOT];
+#pragma unroll
+  for (int l = 0; l < NSLOT; ++l) {
+    const int s = tid + l * GNT;
+    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
+    int x = (x0 - 2 + hx) % g.nx;
+    x += (x < 0) ? g.nx : 0;
+    int y = (y0 - 2 + hy) % g.ny;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
+    sl[l] = hy * GHX + hx;
+  }
+  auto zoff = [&](int z) {
+    z += (z < 0) ? g.nz : 0;
+    z -= (z >= g.nz) ? g.nz : 0;
+    return (long long)z * g.plane;
+  };
+  T pre[NSLOT][PAIRS ? 2 : 1][NP];
+  auto fetch = [&](int z) {
+    const long long zo = zoff(z);
+#pragma unroll
+    for (int l = 0; l < NSLOT; ++l)
+      if (tid + l * GNT < NRUN) {
+#pragma unroll
+        for (int f = 0; f < NP; ++f) {
+          if constexpr (PAIRS) {
+            const T2 v = *reinterpret_cast<const T2*>(op.psrc(f) + zo + off[l]);
+            pre[l][0][f] = v.x;
+            pre[l][PAIRS ? 1 : 0][f] = v.y;
+          } else {
+            pre[l][0][f] = op.psrc(f)[zo + off[l]];
+          }
+        }
+      }
+  };
+  auto stash = [&](int z) {
+    T* P = lds[(z - z0) & 1];
+#pragma unroll
+    for (int l = 0; l < NSLOT; ++l)
+      if (tid + l * GNT < NRUN) {
+#pragma unroll
+        for (int f = 0; f < NP; ++f) {
+          if constexpr (PAIRS)
+            *reinterpret_cast<T2*>(&P[f * GNP + sl[l]]) = T2{pre[l][0][f], pre[l][PAIRS ? 1 : 0][f]};
+          else
+            P[f * GNP + sl[l]] = pre[l][0][f];
+        }
+      }
+  };
+  auto zload = [&](int z, T (&v)[NZ]) {
+    const long long i = zoff(z) + col_off;
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) v[k] = valid ? op.zsrc(k)[i] : T(0);
+  };
+  // zw[0..4]: the own column's z-fields of planes c - 2 .. c + 2; zn: plane
+  // c + 3, requested one plane before it enters the window
+  T zw[5][NZ], zn[NZ];
+  zload(z0 - 2, zw[1]);
+  zload(z0 - 1, zw[2]);
+  zload(z0, zw[3]);
+  zload(z0 + 1, zw[4]);
+  zload(z0 + 2, zn);
+  fetch(z0);
+
+#pragma nounroll
+  for (int cz = z0; cz < z1; ++cz) {
+    stash(cz);
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) zw[s][k] = zw[s + 1][k];
+      zw[4][k] = zn[k];
+    }
+    __syncthreads();
+    const long long id = zoff(cz) + col_off;
+    typename Op::Early early;
+    if (valid) op.early(id, early);
+    if (cz + 1 < z1) {
+      fetch(cz + 1);
+      zload(cz + 3, zn);
+    }
+    if (valid) {
+      const NbrsZ<T, NP, NZ> nbr{lds[(cz - z0) & 1], zw, own};
+      op.emit(nbr, id, early);
+    }
+  }
+}
+
+template <class T, class Op>
+hipError_t launch_march_z(const Grid& g, const Op& op, hipStream_t st) {
+  const PlaneMarch pm = plane_march(g);
+  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
+  const dim3 grid((unsigned)pm.blocks), block(GNT);
+  if (g.nx % 2 == 0)
+    hipLaunchKernelGGL((plane_march_z_kernel<T, Op, true>), grid, block, 0, st, g, pm, remap, op);
+  else
+    hipLaunchKernelGGL((plane_march_z_kernel<T, Op, false>), grid, block, 0, st, g, pm, remap, op);
+  return hipGetLastError();
+}
+
 // Operators that read nothing at the output point.
 struct NoEarly {
   struct Early {};
@@ -553,25 +707,35 @@ struct GatherOp {
 // ---------------------------------------------------------------------------
 template <class T>
 struct ViscOp {
-  static constexpr int NL = W_FIELDS, NF = W_FIELDS, kWavesPerEU = 1;
+  // workspace fields differenced along x or y (plane fields) and along z
+  // (z-fields): G_bar_ad with a or d = x, y; sigma_x, sigma_y, tau_x, tau_y;
+  // and G_bar_az, sigma_z, tau_z
+  static constexpr int NP = 9, NZ = 5, kWavesPerEU = 2;
+  static constexpr int plane_field(int p) { return p < 2 ? W_GB + p : p < 7 ? p + 1 : p + 2; }
+  static constexpr int z_field(int k) { return k == 0 ? W_GB + 2 : k < 3 ? W_GB + k + 3 : k == 3 ? W_SIG + 2 : W_TAU + 2; }
+  static constexpr int plane_slot(int w) { return w < 2 ? w : w < 8 ? w - 1 : w - 2; }
+  static constexpr int z_slot(int w) { return w == W_GB + 2 ? 0 : w < W_SIG ? w - 3 : w == W_SIG + 2 ? 3 : 4; }
   Grid g;
   Coef<T> c;
   const T* __restrict__ q;
   const T* __restrict__ rb;
   const T* __restrict__ w;
   T* __restrict__ qbar;
-  __device__ __forceinline__ const T* src(int f) const { return w + f * g.N; }
-  __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
-#pragma unroll
-    for (int f = 0; f < NL; ++f) o[f] = v[f];
+  __device__ __forceinline__ const T* psrc(int p) const { return w + plane_field(p) * g.N; }
+  __device__ __forceinline__ const T* zsrc(int k) const { return w + z_field(k) * g.N; }
+  template <int d>
+  __device__ __forceinline__ T D(const NbrsZ<T, NP, NZ>& n, int f) const {
+    if constexpr (d == 2) {
+      const int k = z_slot(f);
+      return first_diff(n.atz(k, 0), n.atz(k, 1), n.atz(k, 2), n.atz(k, 3), c.c1[d]);
+    } else {
+      const int p = plane_slot(f);
+      return first_diff(n.template at<d>(p, 0), n.template at<d>(p, 1), n.template at<d>(p, 2),
+                        n.template at<d>(p, 3), c.c1[d]);
+    }
   }
   template <int d>
-  __device__ __forceinline__ T D(const Nbrs<T, NF>& n, int f) const {
-    return first_diff(n.template at<d>(f, 0), n.template at<d>(f, 1), n.template at<d>(f, 2), n.template at<d>(f, 3),
-                      c.c1[d]);
-  }
-  template <int d>
-  __device__ __forceinline__ void direction(const Nbrs<T, NF>& n, T (&ub)[3], T (&X)[3]) const {
+  __device__ __forceinline__ void direction(const NbrsZ<T, NP, NZ>& n, T (&ub)[3], T (&X)[3]) const {
 #pragma unroll
     for (int a = 0; a < 3; ++a) ub[a] -= D<d>(n, W_GB + sym(a, d));
     X[d] = D<d>(n, W_SIG + d);
@@ -590,7 +754,7 @@ struct ViscOp {
 #pragma unroll
     for (int f = 0; f < 4; ++f) e.qb[f] = qbar[f * N + id];
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early& e) const {
+  __device__ __forceinline__ void emit(const NbrsZ<T, NP, NZ>& n, long long id, const Early& e) const {
     const long long N = g.N;
     T ub[3] = {0, 0, 0}, X[3];
     direction<0>(n, ub, X);
@@ -713,7 +877,7 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   if (e != hipSuccess || !c.viscous) return e;
   e = launch_march<T>(g, StressOp<T>{{}, g, c, qq, rr, w}, st);
   if (e != hipSuccess) return e;
-  return launch_march<T>(g, ViscOp<T>{g, c, qq, rr, w, qb}, st);
+  return launch_march_z<T>(g, ViscOp<T>{g, c, qq, rr, w, qb}, st);
 }
 
 template <class T>
