@@ -407,6 +407,173 @@ hipError_t launch_march_z(const Grid& g, const Op& op, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Plane march with two thread roles per column, for an operator too large in
+// registers for two waves of one role per SIMD: a block of 2 x 256 threads
+// (one wave of each role per SIMD, at most 256 registers each).  Role 0
+// evaluates the x and y terms of the output point and completes it; role 1
+// stages the planes, keeps the own column's z-window and evaluates the z
+// terms, whose NA partial sums it hands over through LDS.  Two barriers per
+// plane: after the staging, and after the hand-over.
+// ---------------------------------------------------------------------------
+template <class T, class Op, bool PAIRS>
+__global__ void __launch_bounds__(2 * GNT, 1) plane_march_split_kernel(Grid g, PlaneMarch pm, int remap, Op op) {
+  constexpr int NF = Op::NF, NL = Op::NL, NA = Op::NA;
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  constexpr int NSLOT = PAIRS ? 1 : GLOADS;
+  constexpr int NRUN = PAIRS ? GNP / 2 : GNP;
+  constexpr int RX = PAIRS ? GHX / 2 : GHX;
+  static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
+  __shared__ __align__(16) T lds[GSLOTS][NF * GNP];
+  __shared__ T xch[NA][GNT];
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
+  const int x0 = (b % pm.tiles_x) * GTX;
+  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
+  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  const int z1 = min(z0 + pm.kz, g.nz);
+  const int tid = threadIdx.x % GNT;
+  const bool stager = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / GNT)) == 1;  // role 1
+  const int lx = tid % GTX, ly = tid / GTX;
+  const int cx = x0 + lx, cy = y0 + ly;
+  const bool valid = cx < g.nx && cy < g.ny;
+  const long long col_off = (long long)cy * g.nx + cx;
+  const int own = (ly + 2) * GHX + (lx + 2);
+
+  long long off[NSLOT];
+  int sl[NSLOT];
+#pragma unroll
+  for (int l = 0; l < NSLOT; ++l) {
+    const int s = tid + l * GNT;
+    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
+    int x = (x0 - 2 + hx) % g.nx;
+    x += (x < 0) ? g.nx : 0;
+    int y = (y0 - 2 + hy) % g.ny;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
+    sl[l] = hy * GHX + hx;
+  }
+  auto zoff = [&](int z) {
+    z += (z < 0) ? g.nz : 0;
+    z -= (z >= g.nz) ? g.nz : 0;
+    return (long long)z * g.plane;
+  };
+  T pre[NSLOT][PAIRS ? 2 : 1][NL];
+  auto fetch = [&](int z) {
+    const long long zo = zoff(z);
+#pragma unroll
+    for (int l = 0; l < NSLOT; ++l)
+      if (tid + l * GNT < NRUN) {
+        if constexpr (PAIRS) {
+#pragma unroll
+          for (int f = 0; f < NL; ++f) {
+            const T2 v = *reinterpret_cast<const T2*>(op.src(f) + zo + off[l]);
+            pre[l][0][f] = v.x;
+            pre[l][PAIRS ? 1 : 0][f] = v.y;
+          }
+        } else {
+          load_point<T>(op, zo + off[l], pre[l][0]);
+        }
+      }
+  };
+  auto stash = [&](int z) {
+    T* P = lds[(z - z0 + 3) % GSLOTS];
+#pragma unroll
+    for (int l = 0; l < NSLOT; ++l) {
+      if (tid + l * GNT < NRUN) {
+        if constexpr (PAIRS) {
+          T v0[NF], v1[NF];
+          op.derive(pre[l][0], v0);
+          op.derive(pre[l][PAIRS ? 1 : 0], v1);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) *reinterpret_cast<T2*>(&P[f * GNP + sl[l]]) = T2{v0[f], v1[f]};
+        } else {
+          T v[NF];
+          op.derive(pre[l][0], v);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) P[f * GNP + sl[l]] = v[f];
+        }
+      }
+    }
+  };
+  // Each role runs a loop of its own (the role is wave-uniform and held in a
+  // scalar register, so every wave takes one branch), with two barriers per
+  // plane in both: the registers one role carries from plane to plane are then
+  // not held through the other's code.
+  if (stager) {
+    T wm2[NF], wm1[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) wm2[f] = wm1[f] = T(0);
+    if (valid) {
+      T raw[NL];
+      load_point<T>(op, zoff(z0 - 2) + col_off, raw);
+      op.derive(raw, wm2);
+      load_point<T>(op, zoff(z0 - 1) + col_off, raw);
+      op.derive(raw, wm1);
+    }
+    fetch(z0);
+    stash(z0);
+    fetch(z0 + 1);
+    stash(z0 + 1);
+    fetch(z0 + 2);
+#pragma nounroll
+    for (int cz = z0; cz < z1; ++cz) {
+      stash(cz + 2);
+      __syncthreads();
+      const T* Pc = lds[(cz - z0 + 3) % GSLOTS];
+      if (cz + 3 <= z1 + 1) fetch(cz + 3);
+      if (valid) {
+        const Nbrs<T, NF> nbr{Pc, lds[(cz + 1 - z0 + 3) % GSLOTS], lds[(cz + 2 - z0 + 3) % GSLOTS], wm1, wm2, own};
+        T h[NA];
+        op.along_z(nbr, h);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) xch[k][tid] = h[k];
+      }
+      // the own column of plane c moves to the registers before its slot is
+      // overwritten by plane c + 3
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        wm2[f] = wm1[f];
+        wm1[f] = Pc[f * GNP + own];
+      }
+      __syncthreads();
+    }
+  } else {
+#pragma nounroll
+    for (int cz = z0; cz < z1; ++cz) {
+      __syncthreads();
+      const long long id = zoff(cz) + col_off;
+      typename Op::Early early;
+      typename Op::Acc acc;
+      if (valid) {
+        op.early(id, early);
+        const Nbrs<T, NF> nbr{lds[(cz - z0 + 3) % GSLOTS], nullptr, nullptr, nullptr, nullptr, own};
+        op.in_plane(nbr, acc);
+      }
+      __syncthreads();
+      if (valid) {
+        T h[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) h[k] = xch[k][tid];
+        op.finish(acc, h, id, early);
+      }
+    }
+  }
+}
+
+template <class T, class Op>
+hipError_t launch_march_split(const Grid& g, const Op& op, hipStream_t st) {
+  const PlaneMarch pm = plane_march(g);
+  const int remap = pm.blocks % 8 == 0 ? 1 : 0;
+  const dim3 grid((unsigned)pm.blocks), block(2 * GNT);
+  if (g.nx % 2 == 0)
+    hipLaunchKernelGGL((plane_march_split_kernel<T, Op, true>), grid, block, 0, st, g, pm, remap, op);
+  else
+    hipLaunchKernelGGL((plane_march_split_kernel<T, Op, false>), grid, block, 0, st, g, pm, remap, op);
+  return hipGetLastError();
+}
+
 // Operators that read nothing at the output point.
 struct NoEarly {
   struct Early {};
@@ -485,8 +652,9 @@ struct StressOp : NoEarly {
 //   8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2}),
 //   16 ((f_{+1} - f_0) + (f_{-1} - f_0)) - ((f_{+2} - f_0) + (f_{-2} - f_0))
 // (the factors 8 and 16 are exact), the neighbour differences always taken
-// first.  One block of 256 threads per CU in FP64 (its LDS ring is 114 KB),
-// so each wave may use up to 512 registers.
+// first.  It runs on the two-role march: the x and y directions in one
+// thread, the z direction in another, whose sums join before the chain
+// through the primitive variables (linear in them).
 // ---------------------------------------------------------------------------
 enum { G_Q = 0, G_R = 5, G_IR = 10 };
 
@@ -620,7 +788,7 @@ __device__ __forceinline__ void direction_adjoint(const DirSums<T>& S, bool visc
 
 template <class T>
 struct GatherOp {
-  static constexpr int NL = 10, NF = 11, kWavesPerEU = 1;  // (q, R_bar) -> (q, R_bar, 1/rho)
+  static constexpr int NL = 10, NF = 11;  // (q, R_bar) -> (q, R_bar, 1/rho)
   Grid g;
   Coef<T> c;
   const T* __restrict__ q;
@@ -648,9 +816,8 @@ struct GatherOp {
 #pragma unroll
     for (int f = 0; f < 5; ++f) e.qb[f] = qbar[f * g.N + id];
   }
-  __device__ __forceinline__ void emit(const Nbrs<T, NF>& n, long long id, const Early& e) const {
-    const bool viscous = c.viscous != 0;
-    Centre<T> C;
+  // centre values of the output point, accumulators cleared
+  __device__ __forceinline__ void centre(const Nbrs<T, NF>& n, Centre<T>& C) const {
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       C.q0[f] = n.c(G_Q + f);
@@ -670,9 +837,46 @@ struct GatherOp {
     C.T0 = c.gm2 * C.p0 * C.ir0;
     C.pb = 0;
     C.Tb = 0;
+  }
+  // Accumulators handed from the z role to the in-plane role: q_bar 5, u_bar
+  // 3, p_bar, T_bar, the Laplacian pieces 3 and X 3; every direction adds to
+  // them, and the chain through the primitive variables is linear in them.
+  static constexpr int NA = 16;
+  using Acc = Centre<T>;
+  __device__ __forceinline__ void in_plane(const Nbrs<T, NF>& n, Centre<T>& C) const {
+    const bool viscous = c.viscous != 0;
+    centre(n, C);
     direction<0>(n, viscous, C);
     direction<1>(n, viscous, C);
+  }
+  __device__ __forceinline__ void along_z(const Nbrs<T, NF>& n, T (&h)[NA]) const {
+    const bool viscous = c.viscous != 0;
+    Centre<T> C;
+    centre(n, C);
     direction<2>(n, viscous, C);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) h[f] = C.qb[f];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      h[5 + a] = C.ub[a];
+      h[10 + a] = C.lap[a];
+      h[13 + a] = C.X[a];
+    }
+    h[8] = C.pb;
+    h[9] = C.Tb;
+  }
+  __device__ __forceinline__ void finish(Centre<T>& C, const T (&h)[NA], long long id, const Early& e) const {
+    const bool viscous = c.viscous != 0;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) C.qb[f] += h[f];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C.ub[a] += h[5 + a];
+      C.lap[a] += h[10 + a];
+      C.X[a] += h[13 + a];
+    }
+    C.pb += h[8];
+    C.Tb += h[9];
     const T half = T(0.5);
     if (viscous) {
       // pointwise part of sum_a u_a V_{m_a}: the Laplacian and the D2_a u_a
@@ -873,7 +1077,7 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
   T* qb = static_cast<T*>(qbar);
-  hipError_t e = launch_march<T>(g, GatherOp<T>{g, c, qq, rr, qb}, st);
+  hipError_t e = launch_march_split<T>(g, GatherOp<T>{g, c, qq, rr, qb}, st);
   if (e != hipSuccess || !c.viscous) return e;
   e = launch_march<T>(g, StressOp<T>{{}, g, c, qq, rr, w}, st);
   if (e != hipSuccess) return e;
