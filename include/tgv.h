@@ -215,10 +215,11 @@ int flow_integrals(const ns_params_t* params, const ns_prec_t* prec, const void*
 int flow_integrals_noalloc(const ns_params_t* params, const ns_prec_t* prec, const void* q, double* out8,
                            void* stream);
 
-/* Bytes of device workspace ns_residual_adjoint() needs: 12 fields of N values
+/* Bytes of device workspace ns_residual_adjoint() needs: 15 fields of N values
  * of prec->q's type (the symmetric viscous-work adjoint and the inner
  * differences of the mixed derivatives, read at stencil neighbours by a later
- * pass; only the viscous residual uses it). */
+ * pass, and the velocity adjoint of those terms; only the viscous residual
+ * uses it). */
 size_t ns_residual_adjoint_workspace_bytes(const ns_params_t* params, const ns_prec_t* prec);
 
 /* Discrete adjoint of ns_residual at state q:  q_bar += (dR/dQ)(q)^T r_bar.

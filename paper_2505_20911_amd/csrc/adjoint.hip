@@ -5,18 +5,21 @@
 // D^T = -D, D2^T = D2 and (D_a D_b)^T = D_a D_b on the periodic grid, every
 // stencil term of the forward residual turns into a stencil of R_bar-weighted
 // pointwise fields evaluated around the output point, plus pointwise terms.
-// Passes, each a z-march over LDS-staged planes (plane_march_kernel):
+// Passes, each a z-march over LDS-staged planes, in this order:
+//   for the viscous residual, pass A stores in a caller-provided workspace
+//     the adjoint of the viscous work sum tau_ad G_ad, the symmetric
+//     G_bar_ad = 2 R_bar_E tau_ad (6 components), and the inner derivatives
+//     of the mixed second-derivative terms, sigma_a = sum_{b != a} D_b u_b
+//     and tau_b = sum_{a != b} D_a V_bar_a, so that D_a D_b u_b and
+//     (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one more first difference
+//     each in pass C (D_a and D_b commute on the periodic grid);
+//   pass C gathers those workspace terms into u_bar_a and stores it in 3
+//     more workspace fields;
 //   pass B gathers every transposed-stencil and pointwise contribution that
 //     needs only Q and R_bar, re-deriving u_a, V_bar_a = R_bar_{m_a} +
-//     R_bar_E u_a and sum_f R_bar_f Q_f at each neighbour;
-//   for the viscous residual, pass A stores in a caller-provided workspace
-//     of 12 fields the adjoint of the viscous work sum tau_ad G_ad, the
-//     symmetric G_bar_ad = 2 R_bar_E tau_ad (6 components), and the inner
-//     derivatives of the mixed second-derivative terms, sigma_a =
-//     sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a, so that
-//     D_a D_b u_b and (D_a D_b)^T V_bar_a = D_b D_a V_bar_a become one more
-//     first difference each in pass C (D_a and D_b commute on the periodic
-//     grid); pass C gathers those workspace terms.
+//     R_bar_E u_a and sum_f R_bar_f Q_f at each neighbour, adds pass C's
+//     u_bar_a, and chains the sum through the primitive variables into q_bar
+//     (the only pass that reads and writes q_bar).
 // 1/rho is the hardware reciprocal refined by Newton-Raphson, as in the
 // forward residual.
 #include "tgv_device.h"
@@ -39,8 +42,9 @@ __device__ __forceinline__ int sym(int a, int d) {
 // Workspace layout (viscous residual only), fields of N values each: the
 // symmetric G_bar_ad = 2 R_bar_E tau_ad and the inner first differences
 // sigma_a = sum_{b != a} D_b u_b and tau_b = sum_{a != b} D_a V_bar_a of the
-// mixed second-derivative terms.
-enum { W_GB = 0, W_SIG = 6, W_TAU = 9, W_FIELDS = 12 };
+// mixed second-derivative terms (pass A), and the workspace terms' u_bar_a
+// (pass C).
+enum { W_GB = 0, W_SIG = 6, W_TAU = 9, W_UB = 12, W_FIELDS = 15 };
 static_assert(W_FIELDS == kResidualAdjointWorkFields, "workspace size");
 
 // ---------------------------------------------------------------------------
@@ -794,6 +798,7 @@ struct GatherOp {
   const T* __restrict__ q;
   const T* __restrict__ rb;
   T* __restrict__ qbar;
+  const T* __restrict__ ubv;  // pass C's u_bar (3 fields), viscous only
   __device__ __forceinline__ const T* src(int f) const { return f < G_R ? q + f * g.N : rb + (f - G_R) * g.N; }
   __device__ __forceinline__ void derive(const T (&v)[NL], T (&o)[NF]) const {
 #pragma unroll
@@ -810,11 +815,13 @@ struct GatherOp {
     direction_adjoint<d>(S, viscous, c, C);
   }
   struct Early {
-    T qb[5];
+    T qb[5], ub[3];
   };
   __device__ __forceinline__ void early(long long id, Early& e) const {
 #pragma unroll
     for (int f = 0; f < 5; ++f) e.qb[f] = qbar[f * g.N + id];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e.ub[a] = ubv ? ubv[a * g.N + id] : T(0);
   }
   // centre values of the output point, accumulators cleared
   __device__ __forceinline__ void centre(const Nbrs<T, NF>& n, Centre<T>& C) const {
@@ -880,7 +887,7 @@ struct GatherOp {
     const T half = T(0.5);
     if (viscous) {
       // pointwise part of sum_a u_a V_{m_a}: the Laplacian and the D2_a u_a
-      // part of X_a (its mixed-derivative part is added by pass C)
+      // part of X_a (its mixed-derivative part comes from pass C)
 #pragma unroll
       for (int a = 0; a < 3; ++a) C.ub[a] += C.r0[4] * (c.ire * (C.lap[a] + C.X[a] * T(1.0 / 3.0)));
     }
@@ -895,6 +902,7 @@ struct GatherOp {
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      C.ub[a] += e.ub[a];  // the workspace terms (pass C)
       C.qb[a + 1] += C.ub[a] * C.ir0;
       C.qb[0] -= C.ub[a] * C.u0[a] * C.ir0;
     }
@@ -907,7 +915,8 @@ struct GatherOp {
 // Pass C (viscous only): the workspace terms.  u_bar_a gets the viscous-work
 // adjoint -sum_d D_d(G_bar_ad) and (1/(3 Re)) D_a tau_a, and the mixed part of
 // the forward X_a = D_a sigma_a enters through R_bar_E (1/Re) X_a / 3; the
-// result is chained through u = m / rho into q_bar.
+// result goes to the workspace fields W_UB, which pass B adds to its own u_bar
+// before chaining through u = m / rho into q_bar.
 // ---------------------------------------------------------------------------
 template <class T>
 struct ViscOp {
@@ -921,10 +930,9 @@ struct ViscOp {
   static constexpr int z_slot(int w) { return w == W_GB + 2 ? 0 : w < W_SIG ? w - 3 : w == W_SIG + 2 ? 3 : 4; }
   Grid g;
   Coef<T> c;
-  const T* __restrict__ q;
   const T* __restrict__ rb;
   const T* __restrict__ w;
-  T* __restrict__ qbar;
+  T* __restrict__ ubw;  // = w + W_UB N, disjoint from the fields read
   __device__ __forceinline__ const T* psrc(int p) const { return w + plane_field(p) * g.N; }
   __device__ __forceinline__ const T* zsrc(int k) const { return w + z_field(k) * g.N; }
   template <int d>
@@ -947,32 +955,16 @@ struct ViscOp {
     ub[d] += c.ire * T(1.0 / 3.0) * D<d>(n, W_TAU + d);
   }
   struct Early {
-    T rE, rho, m[3], qb[4];
+    T rE;
   };
-  __device__ __forceinline__ void early(long long id, Early& e) const {
-    const long long N = g.N;
-    e.rE = rb[4 * N + id];
-    e.rho = q[id];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) e.m[a] = q[(a + 1) * N + id];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) e.qb[f] = qbar[f * N + id];
-  }
+  __device__ __forceinline__ void early(long long id, Early& e) const { e.rE = rb[4 * g.N + id]; }
   __device__ __forceinline__ void emit(const NbrsZ<T, NP, NZ>& n, long long id, const Early& e) const {
-    const long long N = g.N;
     T ub[3] = {0, 0, 0}, X[3];
     direction<0>(n, ub, X);
     direction<1>(n, ub, X);
     direction<2>(n, ub, X);
-    const T ir0 = recip(e.rho);
-    T qb0 = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T uba = ub[a] + e.rE * (c.ire * (X[a] * T(1.0 / 3.0)));
-      stream_store(&qbar[(a + 1) * N + id], e.qb[a + 1] + uba * ir0);
-      qb0 -= uba * (e.m[a] * ir0) * ir0;
-    }
-    stream_store(&qbar[id], e.qb[0] + qb0);
+    for (int a = 0; a < 3; ++a) stream_store(&ubw[a * g.N + id], ub[a] + e.rE * (c.ire * (X[a] * T(1.0 / 3.0))));
   }
 };
 
@@ -1077,11 +1069,13 @@ hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* 
   const T* rr = static_cast<const T*>(rbar);
   T* w = static_cast<T*>(work);
   T* qb = static_cast<T*>(qbar);
-  hipError_t e = launch_march_split<T>(g, GatherOp<T>{g, c, qq, rr, qb}, st);
-  if (e != hipSuccess || !c.viscous) return e;
-  e = launch_march<T>(g, StressOp<T>{{}, g, c, qq, rr, w}, st);
-  if (e != hipSuccess) return e;
-  return launch_march_z<T>(g, ViscOp<T>{g, c, qq, rr, w, qb}, st);
+  if (c.viscous) {
+    hipError_t e = launch_march<T>(g, StressOp<T>{{}, g, c, qq, rr, w}, st);
+    if (e != hipSuccess) return e;
+    e = launch_march_z<T>(g, ViscOp<T>{g, c, rr, w, w + W_UB * g.N}, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_march_split<T>(g, GatherOp<T>{g, c, qq, rr, qb, c.viscous ? w + W_UB * g.N : nullptr}, st);
 }
 
 template <class T>

@@ -62,7 +62,7 @@ hipError_t launch_integrals_noalloc(const Grid& g, const Coef<double>& c, const 
                                     hipStream_t st);
 
 // Fields of N values the residual adjoint's workspace holds.
-constexpr int kResidualAdjointWorkFields = 12;
+constexpr int kResidualAdjointWorkFields = 15;
 
 template <class T>
 hipError_t launch_residual_adjoint(const Grid& g, const Coef<T>& c, const void* q, const void* rbar,

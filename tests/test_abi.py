@@ -85,8 +85,8 @@ def test_rejects_bad_scalars():
 
 def test_adjoint_forms_and_workspace_sizes():
     p = tgv.Params(n=(8, 10, 12))
-    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["DP"]) == 12 * p.N * 8
-    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["SP"]) == 12 * p.N * 4
+    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["DP"]) == 15 * p.N * 8
+    assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["SP"]) == 15 * p.N * 4
     assert tgv.ns_residual_adjoint_workspace_bytes(p, tgv.PRESETS["HPSP"]) == 0  # unsupported form
     assert tgv.flow_integrals_adjoint_workspace_bytes(p, tgv.PRESETS["DP"]) == 3 * p.N * 8
     assert tgv.flow_integrals_workspace_bytes(p) >= 8 * 8
