@@ -93,7 +93,7 @@ def attainable(n, reps=5):
     libtgv_probe.so (read + write bytes over the event-timed duration): a
     plain 4 GiB copy, and the fused FP64 stage's memory traffic at n^3 in its
     z-march order (no halo, no arithmetic), with 128 and with 16 planes per
-    block."""
+    block, and the same traffic in plain element order (16 bytes per lane)."""
     import ctypes
     import torch
     path = os.path.join(ROOT, "paper_2505_20911_amd", "libtgv_probe.so")
@@ -102,6 +102,7 @@ def attainable(n, reps=5):
     lib = ctypes.CDLL(path)
     lib.tgv_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_void_p]
     lib.tgv_probe_stage_stream.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
+    lib.tgv_probe_stage_flat.argtypes = [ctypes.c_longlong] + [ctypes.c_void_p] * 4
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def rate(call, nbytes):
@@ -127,6 +128,9 @@ def attainable(n, reps=5):
         out[f"stage_pattern_kz{kz}_gbs"] = rate(
             lambda: lib.tgv_probe_stage_stream(n, kz, 8, q[0].data_ptr(), q[1].data_ptr(), q[2].data_ptr(), st),
             20 * 8 * n ** 3)
+    out["stage_flat_gbs"] = rate(
+        lambda: lib.tgv_probe_stage_flat(n ** 3, q[0].data_ptr(), q[1].data_ptr(), q[2].data_ptr(), st),
+        20 * 8 * n ** 3)
     del q
     torch.cuda.empty_cache()
     return out

@@ -10,7 +10,9 @@
 //                          marching kz planes along z, per point reading 5
 //                          fields of Q_in and of Q~ and writing 5 fields of
 //                          Q_out and of Q~ (layout [5][n][n][n], x fastest),
-//                          tiles x fastest in contiguous runs per XCD.
+//                          tiles x fastest in contiguous runs per XCD;
+//   tgv_probe_stage_flat   the same per-point traffic (FP64) in plain element
+//                          order, two points (16 bytes) per lane and array.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -60,6 +62,25 @@ __global__ void __launch_bounds__(256) probe_stage_kernel(const T* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(256) probe_stage_flat_kernel(const double* __restrict__ qin, double* __restrict__ qt,
+                                                              double* __restrict__ qout, long long N) {
+  const long long i = ((long long)blockIdx.x * 256 + threadIdx.x) * 2;
+  if (i >= N) return;
+  d2 a[5], t[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    a[f] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(qin + f * N + i));
+    t[f] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(qt + f * N + i));
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const d2 t2 = -0.5 * t[f] + 1e-3 * a[f];
+    const d2 q2 = a[f] + 0.3 * t2;
+    __builtin_nontemporal_store(t2, reinterpret_cast<d2*>(qt + f * N + i));
+    __builtin_nontemporal_store(q2, reinterpret_cast<d2*>(qout + f * N + i));
+  }
+}
+
 template <class T>
 int launch_stage(int n, int kz, const void* qin, void* qt, void* qout, hipStream_t st) {
   const int tiles_x = (n + 63) / 64, tiles_y = (n + 3) / 4;
@@ -103,6 +124,20 @@ int tgv_probe_stage_stream(int n, int kz, int elem_bytes, const void* q_in, void
     case 2: return launch_stage<uint16_t>(n, kz, q_in, q_t, q_out, st);
     default: return -1;
   }
+}
+
+// The same traffic as tgv_probe_stage_stream with 8-byte elements over N
+// points (N even, every array 16-byte aligned), in element order.  Returns 0,
+// -1 for a bad argument, -3 for a grid too large, -5 for a launch error.
+int tgv_probe_stage_flat(long long N, const void* q_in, void* q_t, void* q_out, void* stream) {
+  if (N < 2 || N % 2 || !q_in || !q_t || !q_out ||
+      (reinterpret_cast<uintptr_t>(q_in) | reinterpret_cast<uintptr_t>(q_t) | reinterpret_cast<uintptr_t>(q_out)) % 16)
+    return -1;
+  const long long nb = (N / 2 + 255) / 256;
+  if (nb > 0x7fffffffLL) return -3;
+  hipLaunchKernelGGL(probe_stage_flat_kernel, dim3((unsigned)nb), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const double*>(q_in), static_cast<double*>(q_t), static_cast<double*>(q_out), N);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 }  // extern "C"
