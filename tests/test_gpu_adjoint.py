@@ -118,8 +118,9 @@ def test_residual_adjoint_sp_within_rounding(n, kind):
     assert np.all(err <= 64 * u * scale + 2 * u * np.abs(ref))
 
 
-@pytest.mark.parametrize("n", [(12, 16, 10), (5, 6, 7)])
+@pytest.mark.parametrize("n", [(12, 16, 10), (5, 6, 7)] + FULL_LAUNCH_GRIDS)
 def test_integrals_adjoint_matches_oracle(n):
+    say("eps^S adjoint DP", n)
     p = tgv.Params(n=n)
     q64 = S.random_state(n, 8, smooth=True)
     ref = O.integrals_adjoint(oracle_params(p), q64, 0.37)
