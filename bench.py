@@ -429,7 +429,7 @@ def main():
           flush=True)
     head_key = "DP" if "DP" in results else next(iter(results))
     head = results[head_key]
-    stage_rate = max(v for k, v in att.items() if k.startswith("stage"))
+    stage_rate = max(v for k, v in att.items() if k.startswith("stage_pattern"))  # the z-march order the kernel uses
     for key, r in results.items():
         r["speedup_vs_DP"] = r["mpt_stage_per_s"] / head["mpt_stage_per_s"]
         if "fused" in r["kernels"]:
