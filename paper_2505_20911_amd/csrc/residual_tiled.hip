@@ -56,6 +56,15 @@ constexpr int TX = 64, TY = 8, NT = TX * TY;
 // few registers).
 template <class Tc>
 constexpr int kWavesPerEU = 2;
+// Waves per SIMD the warp-specialised kernel is compiled for.  The fused
+// stage with FP16 storage and packed FP16 arithmetic fits two 512-thread
+// blocks per CU (59 KB of LDS each) at 128 registers, a few of them spilled:
+// 2.13 against 2.22 ms at 512^3; its residual-only instance spills more and
+// was slower that way (1.86 against 1.52 ms), so it keeps two waves.
+template <class Tq, class Tc, bool FUSED>
+constexpr int kWsWaves = kWavesPerEU<Tc>;
+template <>
+constexpr int kWsWaves<f16, h2, true> = 4;
 constexpr int HX = TX + 4, HY = TY + 4, NPL = HX * HY;  // LDS plane incl. halo
 // Plane loads in runs of V consecutive x-points per lane (V = 2 when nx is
 // even: a run then never crosses the periodic wrap and is V-element aligned).
@@ -1063,7 +1072,7 @@ __device__ __forceinline__ void z_step(const Kernel<Tq, Tr, Tc>& K, const RkArgs
 }
 
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int WTX, int WTY, int V>
-__global__ void __launch_bounds__((Ws<WTX, WTY>::NT), kWavesPerEU<Tc>) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
+__global__ void __launch_bounds__((Ws<WTX, WTY>::NT), (kWsWaves<Tq, Tc, FUSED>)) residual_ws(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk,
                                                                       int tiles_x, int tiles_y, int kz, int remap) {
   TGV_WS_DIMS
   TGV_WS_RUNS
