@@ -362,7 +362,7 @@ def split_leg(n, steps=5):
     return out
 
 
-def large_leg(n=1024, forms=("DP", "SPDP", "HPSP", "HP_C16"), steps=3):
+def large_leg(n=1024, forms=("DP", "SPDP", "SP_DPC", "HPSP", "HP_C16"), steps=3):
     """The 1024^3 workload (1.07e9 points): fused-stage throughput, kernel
     duration and device memory of a few precision forms over `steps` steps
     after one warm-up step (the step count is cut from the 200 of the full
@@ -441,6 +441,7 @@ def main():
             r["kernels"]["fused"]["frac_of_stage_pattern"] = gbs / stage_rate
     kname = "fused" if head["path"] == "fused" else "residual"
     hk = head["kernels"][kname]
+    traffic = measured_traffic(("ns_residual_rk_stage" if kname == "fused" else "ns_residual") + f"/{head_key}/{n}")
     line = {
         "metric": METRIC,
         "value": head["mpt_stage_per_s"],  # median over the timed regions of the headline form
@@ -462,8 +463,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "ns_residual_rk_stage" if kname == "fused" else "ns_residual",
                      "achieved": hk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": hk["gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(("ns_residual_rk_stage" if kname == "fused" else "ns_residual")
-                                                 + f"/{head_key}/{n}"),
+                     "traffic": traffic,
+                     # the counter bytes over the same duration: the HBM-side share of the peak
+                     "traffic_frac": (traffic / (hk["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "bytes_per_launch": hk["bytes_per_launch"], "avg_launch_ms": hk["avg_ms"],
                      "attainable": att,
                      "frac_of_stage_pattern": hk["gbs"] / stage_rate},
