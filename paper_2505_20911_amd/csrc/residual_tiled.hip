@@ -619,6 +619,42 @@ __device__ __forceinline__ void zstep(const Kernel<Tq, Tr, Tc>& K, const RkArgs<
   __syncthreads();
 }
 
+// Block order.  Hardware block b runs on XCD b % 8 (round robin); the remap
+// gives each XCD a contiguous range of logical tiles.  The logical order walks
+// strips kStripPoints wide across x, x fastest within a strip (on grids up to
+// that width: rows of tiles, x fastest).  The 32 blocks resident on one XCD
+// at a time then cover rows of at most kStripPoints columns, e.g. 2 rows of 16
+// tiles of 32 x 8 columns, whose x- and y-halo loads meet in that XCD's L2; on
+// a 1024-wide grid a whole row of 32 tiles was resident instead, and the
+// stage fetched its Q at the full halo ratio from HBM.
+constexpr int kStripPoints = 512;
+
+struct TileIdx {
+  int tx, ty, cz;
+};
+
+__device__ __forceinline__ TileIdx tile_of_block(int tiles_x, int tiles_y, int tile_w, int remap) {
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nb / 8) + b / 8;
+  const int per_chunk = tiles_x * tiles_y;
+  TileIdx t;
+  t.cz = b / per_chunk;
+  const int r = b % per_chunk;
+  const int sw = max(1, kStripPoints / tile_w);  // strip width in tiles
+  const int full = tiles_x / sw;                 // full-width strips
+  if (r < full * sw * tiles_y) {
+    const int s = r / (sw * tiles_y), i = r % (sw * tiles_y);
+    t.tx = s * sw + i % sw;
+    t.ty = i / sw;
+  } else {
+    const int w = tiles_x - full * sw, i = r - full * sw * tiles_y;
+    t.tx = full * sw + i % w;
+    t.ty = i / w;
+  }
+  return t;
+}
+
 template <class Tq, class Tr, class Tc, class Tqt, class Ta, bool FUSED, int SPLIT, int V>
 __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq, Tr, Tc> K, RkArgs<Tq, Tqt, Ta> rk, int tiles_x,
                                                      int tiles_y, int kz, int remap) {
@@ -626,18 +662,11 @@ __global__ void __launch_bounds__(NT, kWavesPerEU<Tc>) residual_tiled(Kernel<Tq,
   __shared__ Tc lds[NF * NPL];
   __shared__ Tc lds_ri[RI_SLOTS * 5 * NT];
   const Grid& g = K.g;
-  // XCD-aware order: hardware block b runs on XCD b % 8; give each XCD a
-  // contiguous range of logical tiles, x fastest, so that the blocks resident
-  // on one XCD at a time cover whole rows of tiles and their x- and y-halo
-  // loads meet in that XCD's L2 (at 512^3: 32 resident tiles = 512 x 32
-  // columns, halo fetch 1.16x the tile's own bytes instead of 1.6x).
-  const int nb = gridDim.x;
-  int b = blockIdx.x;
-  if (remap) b = (b % 8) * (nb / 8) + b / 8;
-  const int tx_t = b % tiles_x;
-  const int ty_t = (b / tiles_x) % tiles_y;
-  const int cz = b / (tiles_y * tiles_x);
-  const int x0 = tx_t * TX, y0 = ty_t * TY;
+  // XCD-aware block order (tile_of_block); at 512^3: 32 resident tiles =
+  // 512 x 32 columns, halo fetch 1.16x the tile's own bytes instead of 1.6x
+  const TileIdx tt = tile_of_block(tiles_x, tiles_y, TX, remap);
+  const int cz = tt.cz;
+  const int x0 = tt.tx * TX, y0 = tt.ty * TY;
   const int z0 = cz * kz;
   const int z1 = min(z0 + kz, g.nz);
 
@@ -1080,13 +1109,9 @@ __global__ void __launch_bounds__((Ws<WTX, WTY>::NT), (kWsWaves<Tq, Tc, FUSED>))
   __shared__ Tc ring_r[RR_SLOTS][5 * WS_NCOL];
   __shared__ Tc ring_a[RA_SLOTS][3 * WS_NCOL];
   const Grid& g = K.g;
-  const int nb = gridDim.x;
-  int b = blockIdx.x;
-  if (remap) b = (b % 8) * (nb / 8) + b / 8;
-  const int tx_t = b % tiles_x;
-  const int ty_t = (b / tiles_x) % tiles_y;
-  const int cz = b / (tiles_y * tiles_x);
-  const int x0 = tx_t * WS_TX * WS_P, y0 = ty_t * WS_TY;  // in grid points
+  const TileIdx tt = tile_of_block(tiles_x, tiles_y, WS_TX * WS_P, remap);
+  const int cz = tt.cz;
+  const int x0 = tt.tx * WS_TX * WS_P, y0 = tt.ty * WS_TY;  // in grid points
   const int z0 = cz * kz;
   const int z1 = min(z0 + kz, g.nz);
   const bool zrole = threadIdx.x >= WS_NCOL;
