@@ -110,6 +110,44 @@ struct Nbrs {
   }
 };
 
+// The tile origin and first plane of this block: hardware block b runs on
+// XCD b % 8, and with remap each XCD takes a contiguous range of tiles.
+__device__ __forceinline__ void tile_origin(const PlaneMarch& pm, int remap, int& x0, int& y0, int& z0) {
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
+  x0 = (b % pm.tiles_x) * GTX;
+  y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
+  z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+}
+
+// Offset of plane z (z in [-nz, 2 nz), wrapped periodically).
+__device__ __forceinline__ long long plane_off(const Grid& g, int z) {
+  z += (z < 0) ? g.nz : 0;
+  z -= (z >= g.nz) ? g.nz : 0;
+  return (long long)z * g.plane;
+}
+
+// The halo-plane runs thread tid of a role stages (one point, or with PAIRS
+// two x-points): each run's offset within a plane and LDS index of its first
+// point.
+template <bool PAIRS, int NSLOT>
+__device__ __forceinline__ void halo_runs(const Grid& g, int x0, int y0, int tid, long long (&off)[NSLOT],
+                                          int (&sl)[NSLOT]) {
+  constexpr int RX = PAIRS ? GHX / 2 : GHX;
+#pragma unroll
+  for (int l = 0; l < NSLOT; ++l) {
+    const int s = tid + l * GNT;
+    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
+    int x = (x0 - 2 + hx) % g.nx;
+    x += (x < 0) ? g.nx : 0;
+    int y = (y0 - 2 + hy) % g.ny;
+    y += (y < 0) ? g.ny : 0;
+    off[l] = (long long)y * g.nx + x;
+    sl[l] = hy * GHX + hx;
+  }
+}
+
 // The NL values of one point, field f read from op.src(f) at offset i.
 template <class T, class Op>
 __device__ __forceinline__ void load_point(const Op& op, long long i, T (&v)[Op::NL]) {
@@ -128,15 +166,10 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   typedef T T2 __attribute__((ext_vector_type(2)));
   constexpr int NSLOT = PAIRS ? 1 : GLOADS;  // load slots per thread
   constexpr int NRUN = PAIRS ? GNP / 2 : GNP;  // runs per plane
-  constexpr int RX = PAIRS ? GHX / 2 : GHX;    // runs per halo row
   static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
   __shared__ __align__(16) T lds[GSLOTS][NF * GNP];
-  const int nblk = gridDim.x;
-  int b = blockIdx.x;
-  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
-  const int x0 = (b % pm.tiles_x) * GTX;
-  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
-  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  int x0, y0, z0;
+  tile_origin(pm, remap, x0, y0, z0);
   const int z1 = min(z0 + pm.kz, g.nz);
   const int tid = threadIdx.x;
   const int lx = tid % GTX, ly = tid / GTX;
@@ -145,26 +178,11 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_kernel(Grid 
   const long long col_off = (long long)cy * g.nx + cx;
   const int own = (ly + 2) * GHX + (lx + 2);
 
-  // the halo-plane runs this thread stages: grid offset and LDS index of the
-  // run's first point
+  // the halo-plane runs this thread stages
   long long off[NSLOT];
   int sl[NSLOT];
-#pragma unroll
-  for (int l = 0; l < NSLOT; ++l) {
-    const int s = tid + l * GNT;
-    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
-    int x = (x0 - 2 + hx) % g.nx;
-    x += (x < 0) ? g.nx : 0;
-    int y = (y0 - 2 + hy) % g.ny;
-    y += (y < 0) ? g.ny : 0;
-    off[l] = (long long)y * g.nx + x;
-    sl[l] = hy * GHX + hx;
-  }
-  auto zoff = [&](int z) {
-    z += (z < 0) ? g.nz : 0;
-    z -= (z >= g.nz) ? g.nz : 0;
-    return (long long)z * g.plane;
-  };
+  halo_runs<PAIRS>(g, x0, y0, tid, off, sl);
+  auto zoff = [&](int z) { return plane_off(g, z); };
   T pre[NSLOT][PAIRS ? 2 : 1][NL];
   auto fetch = [&](int z) {
     const long long zo = zoff(z);
@@ -293,15 +311,10 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_z_kernel(Gri
   typedef T T2 __attribute__((ext_vector_type(2)));
   constexpr int NSLOT = PAIRS ? 1 : GLOADS;
   constexpr int NRUN = PAIRS ? GNP / 2 : GNP;
-  constexpr int RX = PAIRS ? GHX / 2 : GHX;
   static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
   __shared__ __align__(16) T lds[2][NP * GNP];
-  const int nblk = gridDim.x;
-  int b = blockIdx.x;
-  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
-  const int x0 = (b % pm.tiles_x) * GTX;
-  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
-  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  int x0, y0, z0;
+  tile_origin(pm, remap, x0, y0, z0);
   const int z1 = min(z0 + pm.kz, g.nz);
   const int tid = threadIdx.x;
   const int lx = tid % GTX, ly = tid / GTX;
@@ -312,22 +325,8 @@ __global__ void __launch_bounds__(GNT, Op::kWavesPerEU) plane_march_z_kernel(Gri
 
   long long off[NSLOT];
   int sl[NSLOT];
-#pragma unroll
-  for (int l = 0; l < NSLOT; ++l) {
-    const int s = tid + l * GNT;
-    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
-    int x = (x0 - 2 + hx) % g.nx;
-    x += (x < 0) ? g.nx : 0;
-    int y = (y0 - 2 + hy) % g.ny;
-    y += (y < 0) ? g.ny : 0;
-    off[l] = (long long)y * g.nx + x;
-    sl[l] = hy * GHX + hx;
-  }
-  auto zoff = [&](int z) {
-    z += (z < 0) ? g.nz : 0;
-    z -= (z >= g.nz) ? g.nz : 0;
-    return (long long)z * g.plane;
-  };
+  halo_runs<PAIRS>(g, x0, y0, tid, off, sl);
+  auto zoff = [&](int z) { return plane_off(g, z); };
   T pre[NSLOT][PAIRS ? 2 : 1][NP];
   auto fetch = [&](int z) {
     const long long zo = zoff(z);
@@ -428,16 +427,11 @@ __global__ void __launch_bounds__(2 * GNT, sizeof(T) == 4 ? 4 : 2) plane_march_s
   typedef T T2 __attribute__((ext_vector_type(2)));
   constexpr int NSLOT = PAIRS ? 1 : GLOADS;
   constexpr int NRUN = PAIRS ? GNP / 2 : GNP;
-  constexpr int RX = PAIRS ? GHX / 2 : GHX;
   static_assert(!PAIRS || (GHX % 2 == 0 && NRUN <= GNT), "one run per thread");
   __shared__ __align__(16) T lds[GSLOTS][NF * GNP];
   __shared__ T xch[NA][GNT];
-  const int nblk = gridDim.x;
-  int b = blockIdx.x;
-  if (remap) b = (b % 8) * (nblk / 8) + b / 8;
-  const int x0 = (b % pm.tiles_x) * GTX;
-  const int y0 = ((b / pm.tiles_x) % pm.tiles_y) * GTY;
-  const int z0 = (b / (pm.tiles_x * pm.tiles_y)) * pm.kz;
+  int x0, y0, z0;
+  tile_origin(pm, remap, x0, y0, z0);
   const int z1 = min(z0 + pm.kz, g.nz);
   const int tid = threadIdx.x % GNT;
   const bool stager = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / GNT)) == 1;  // role 1
@@ -449,22 +443,8 @@ __global__ void __launch_bounds__(2 * GNT, sizeof(T) == 4 ? 4 : 2) plane_march_s
 
   long long off[NSLOT];
   int sl[NSLOT];
-#pragma unroll
-  for (int l = 0; l < NSLOT; ++l) {
-    const int s = tid + l * GNT;
-    const int hy = s / RX, hx = (s % RX) * (PAIRS ? 2 : 1);
-    int x = (x0 - 2 + hx) % g.nx;
-    x += (x < 0) ? g.nx : 0;
-    int y = (y0 - 2 + hy) % g.ny;
-    y += (y < 0) ? g.ny : 0;
-    off[l] = (long long)y * g.nx + x;
-    sl[l] = hy * GHX + hx;
-  }
-  auto zoff = [&](int z) {
-    z += (z < 0) ? g.nz : 0;
-    z -= (z >= g.nz) ? g.nz : 0;
-    return (long long)z * g.plane;
-  };
+  halo_runs<PAIRS>(g, x0, y0, tid, off, sl);
+  auto zoff = [&](int z) { return plane_off(g, z); };
   T pre[NSLOT][PAIRS ? 2 : 1][NL];
   auto fetch = [&](int z) {
     const long long zo = zoff(z);
